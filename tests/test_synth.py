@@ -1,0 +1,41 @@
+"""Seeded generators: determinism and the shape of the synthetic workloads."""
+import numpy as np
+
+from paper_2404_19638_amd import synth
+
+
+def test_uniform_stream_is_deterministic_and_in_range():
+    a = synth.uniform_f32(99, 100_000)
+    b = synth.uniform_f32(99, 100_000)
+    assert a.tobytes() == b.tobytes()
+    assert a.min() >= -1.0 and a.max() < 1.0
+    assert abs(float(a.mean())) < 0.01
+    # offsets address the same stream
+    np.testing.assert_array_equal(synth.uniform_f32(99, 10, ctr0=500), a[500:510])
+
+
+def test_dense_indexing_by_global_row():
+    full = synth.dense_f32(5, 0, 64, 8)
+    part = synth.dense_f32(5, 40, 10, 8)
+    np.testing.assert_array_equal(full[40:50], part)
+
+
+def test_uniform_block_exact_count_distinct():
+    r, c = synth.uniform_block(4096, 4096, 40_000, 2404)
+    assert r.size == 40_000
+    assert np.unique(r * 4096 + c).size == 40_000
+    r2, c2 = synth.uniform_block(4096, 4096, 40_000, 2404)
+    assert np.array_equal(r, r2) and np.array_equal(c, c2)
+
+
+def test_rmat_block_distinct_in_range_and_skewed():
+    rr, cr = (1 << 12, 2 << 12), (0, 1 << 12)
+    r, c = synth.rmat_block(14, 16 << 14, 77, rr, cr)
+    assert r.size > 0
+    assert r.min() >= rr[0] and r.max() < rr[1] and c.min() >= cr[0] and c.max() < cr[1]
+    assert np.unique((r - rr[0]) * (1 << 12) + (c - cr[0])).size == r.size
+    deg = np.bincount(r - rr[0])
+    deg = deg[deg > 0]
+    assert deg.max() > 8 * deg.mean()          # power-law hubs
+    r2, c2 = synth.rmat_block(14, 16 << 14, 77, rr, cr)
+    assert np.array_equal(r, r2) and np.array_equal(c, c2)
