@@ -1,0 +1,220 @@
+/*
+ * spc3d — the local data-parallel hot path of 3D sparsity-aware SDDMM and
+ * SpMM (SpComm3D, Abubaker and Hoefler) on one AMD Instinct MI355X (gfx950).
+ *
+ * One GPU plays one processor P_{x,y,z} of the paper's 3D grid.  Its work per
+ * iteration is the local part of the three phases the paper defines for every
+ * sparse kernel (Section "The SpComm3D Framework", General structure):
+ *
+ *   setup (once per sparsity pattern)   spc3d_plan_create_coo
+ *       localization of the block S_{x,y}: compact local row/column ids with
+ *       globalMap / localMap, empty rows and columns removed
+ *       (Section "Data distribution");
+ *   PreComm, local side                 spc3d_gather
+ *       pack the dense data units (row slices of A and B over the K-slice)
+ *       that the block's nonzeros touch, SpC-BB style (Section "Sparse
+ *       communication model", Method 1);
+ *   Compute                             spc3d_sddmm, spc3d_spmm
+ *       Eq. (1) and Eq. (2) over the localized block with the K/Z slice
+ *       (Section "Building 3D SDDMM and SpMM Algorithms", The Compute phase);
+ *   PostComm, local side                spc3d_scatter_reduce, and the
+ *       ACCUMULATE mode of spc3d_sddmm for the sum of Z partial results
+ *       (The PostComm phase; SpMM PostComm in "Building SpMM").
+ *
+ * Conventions for every call
+ * --------------------------
+ *  - "d_" pointers are device pointers on the plan's device; the caller owns
+ *    all of them.  The library never allocates or frees device memory: a plan
+ *    lives in a caller-provided workspace, and SpMM scratch space is a
+ *    caller-provided buffer.
+ *  - Every call returns an spc3d_status and never throws or aborts.
+ *    spc3d_last_error() gives a thread-local text for the last failure.
+ *  - Hot-path calls (gather, sddmm, spmm, scatter_reduce, permute, softmax)
+ *    are asynchronous on `stream`; arguments are validated on the host before
+ *    any launch.  Only spc3d_plan_create_coo synchronizes `stream`.
+ *  - Dense row-major layouts: element (r, k) of a matrix with leading
+ *    dimension ld is at offset r*ld + k.  Packed buffers have ld = kz.
+ *  - Slot order: the plan stores the block's entries sorted by (local row,
+ *    local column, caller index).  Values and SDDMM outputs passed to the hot
+ *    calls are in this slot order; spc3d_permute_values converts from and to
+ *    the caller's COO order.
+ *  - Limits: nnz < 2^31; each id range (hi - lo) in [1, 2^31 - 1];
+ *    kz in [1, 1024] (kz not a multiple of the 16-byte vector width is limited
+ *    to 256).
+ *  - Distinct plans on distinct streams are independent.  Calls that share a
+ *    plan only read it, so they may run concurrently unless they also share
+ *    an output or an SpMM buffer.
+ */
+#ifndef SPC3D_H
+#define SPC3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPC3D_OK = 0,
+  SPC3D_ERR_INVALID_ARG = 1,  /* null pointer, bad size, misalignment, bad enum */
+  SPC3D_ERR_OUT_OF_RANGE = 2, /* a global id outside [lo, hi) at plan creation */
+  SPC3D_ERR_WORKSPACE = 3,    /* workspace or buffer smaller than required */
+  SPC3D_ERR_UNSUPPORTED = 4,  /* valid request this build does not implement */
+  SPC3D_ERR_HIP = 5,          /* a HIP runtime call failed */
+  SPC3D_ERR_BAD_HANDLE = 6    /* not a live plan */
+} spc3d_status;
+
+typedef enum { SPC3D_F32 = 0, SPC3D_BF16 = 1 } spc3d_dtype;
+typedef enum { SPC3D_ROWS = 0, SPC3D_COLS = 1 } spc3d_axis;
+
+enum { SPC3D_OVERWRITE = 0, SPC3D_ACCUMULATE = 1 };  /* output modes */
+enum { SPC3D_BUILD_CSC = 1u };                        /* plan flags */
+enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
+
+/* Kernel variant for sddmm / spmm: -1 lets the library choose; otherwise
+ * (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64, 0..4) << 4.
+ * Every valid variant computes the same result within the stated tolerance. */
+#define SPC3D_VARIANT(lg_lanes, lg_items) ((lg_lanes) | ((lg_items) << 4))
+
+typedef struct spc3d_plan_s* spc3d_plan;
+
+/* Device arrays of a plan (read-only views into its workspace).  R, C are the
+ * numbers of non-empty rows / columns.  gmap_*: local -> global id (ascending);
+ * lmap_*[g - lo]: global -> local id or -1; rowptr[R+1], colidx[nnz]: row-major
+ * slots; perm[nnz]: slot -> caller index.  With SPC3D_BUILD_CSC also
+ * colptr[C+1], rowidx_t[nnz] (local row of each column-major slot) and
+ * slot_t[nnz] (row-major slot of each column-major slot); else NULL. */
+typedef struct {
+  const int64_t* gmap_r;
+  const int64_t* gmap_c;
+  const int32_t* lmap_r;
+  const int32_t* lmap_c;
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const int32_t* perm;
+  const int32_t* colptr;
+  const int32_t* rowidx_t;
+  const int32_t* slot_t;
+} spc3d_maps;
+
+/* ------------------------------------------------------------------ setup */
+
+/* Bytes of device workspace spc3d_plan_create_coo needs for a block with nnz
+ * entries, row ids in [row_lo,row_hi) and column ids in [col_lo,col_hi). */
+spc3d_status spc3d_plan_workspace_size(int64_t nnz, int64_t row_lo, int64_t row_hi,
+                                       int64_t col_lo, int64_t col_hi, uint32_t flags,
+                                       size_t* bytes);
+
+/* Localize a block given in COO with global ids (paper: Section "Data
+ * distribution"; the setup phase of Section "General structure").
+ * d_row_gid[nnz], d_col_gid[nnz]: int64 global ids in caller order; repeated
+ * (i,j) pairs are kept as separate entries.  Local ids are ranks of the
+ * distinct ids in ascending order.  d_ws (256-byte aligned, ws_bytes from
+ * spc3d_plan_workspace_size) must outlive the plan and is owned by it until
+ * spc3d_plan_destroy.  Synchronizes `stream`.  Errors: INVALID_ARG,
+ * WORKSPACE, OUT_OF_RANGE (any id outside its range; no plan is created). */
+spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
+                                   const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                                   int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Sizes of a plan: non-empty rows R, non-empty columns C, entries nnz. */
+spc3d_status spc3d_plan_query(spc3d_plan plan, int64_t* R, int64_t* C, int64_t* nnz);
+
+/* Device views of a plan's maps and index arrays (see spc3d_maps). */
+spc3d_status spc3d_plan_maps(spc3d_plan plan, spc3d_maps* maps);
+
+/* Release the host object; the workspace may be reused afterwards. */
+spc3d_status spc3d_plan_destroy(spc3d_plan plan);
+
+/* -------------------------------------------------------------- hot path */
+
+/* PreComm, local side: SpC-BB packing of data units (paper: Section "Sparse
+ * communication model", Method 1).  axis ROWS packs n = R rows, COLS n = C:
+ *   d_packed[l*kz + k] = d_src[(gmap[l] - lo)*ld_src + k0 + k],  l < n, k < kz.
+ * d_src rows are indexed relative to the axis' lo.  src_t F32 -> packed_t F32
+ * (bit copy) or BF16 (round to nearest even; NaN stays NaN with its sign);
+ * src_t BF16 -> packed_t BF16 (bit copy).  Requires 0 <= k0, k0 + kz <= ld_src. */
+spc3d_status spc3d_gather(spc3d_plan plan, spc3d_axis axis, const void* d_src,
+                          spc3d_dtype src_t, int64_t ld_src, int32_t k0, int32_t kz,
+                          void* d_packed, spc3d_dtype packed_t, hipStream_t stream);
+
+/* SDDMM, Eq. (1), over the localized block: for every slot p with local row
+ * i and local column j,
+ *   d_out[p] (=|+=) s_p * sum_{k<kz} A[i*kz + k] * B[j*kz + k]
+ * d_vals[nnz] in slot order (NULL: s == 1, pattern-only sampling); d_A
+ * [R x kz] and d_B [C x kz] packed, of type ab_t (F32, or BF16 with FP32
+ * accumulation); d_out[nnz] FP32 in slot order.  mode OVERWRITE or
+ * ACCUMULATE (adds this K-slice's partial to d_out: the Z-partial sum of the
+ * SDDMM PostComm).  d_out may not alias the inputs. */
+spc3d_status spc3d_sddmm(spc3d_plan plan, const float* d_vals, const void* d_A, const void* d_B,
+                         spc3d_dtype ab_t, int32_t kz, float* d_out, int mode, int variant,
+                         hipStream_t stream);
+
+/* Bytes of scratch spc3d_spmm needs for (transpose, kz, variant). */
+spc3d_status spc3d_spmm_buffer_size(spc3d_plan plan, int transpose, int32_t kz, int variant,
+                                    size_t* bytes);
+
+/* SpMM, Eq. (2), over the localized block:
+ *   transpose = 0:  Y[i*kz + k] (=|+=) sum_{p in row i} s_p * X[j(p)*kz + k],
+ *                   X [C x kz], Y [R x kz];
+ *   transpose = 1:  Y[j*kz + k] (=|+=) sum_{p in column j} s_p * X[i(p)*kz + k],
+ *                   X [R x kz], Y [C x kz]  (needs a plan built with
+ *                   SPC3D_BUILD_CSC; used by the backward of SDDMM / SpMM).
+ * d_vals[nnz] FP32 in slot order (NULL: s == 1).  X of type x_t (F32 or BF16),
+ * accumulation and Y in FP32.  Long rows are split across wavefronts and their
+ * partial sums combined in a fixed order, so results are deterministic.
+ * d_buf (256-byte aligned) holds at least spc3d_spmm_buffer_size bytes.
+ * Y may not alias X. */
+spc3d_status spc3d_spmm(spc3d_plan plan, int transpose, const float* d_vals, const void* d_X,
+                        spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant,
+                        void* d_buf, size_t buf_bytes, hipStream_t stream);
+
+/* PostComm, local side: SpC-BB unpacking with reduction at the owner (paper:
+ * "Building SpMM with SpComm3D", partial A rows sent to their owners):
+ *   d_dst[(gmap[l] - lo)*ld_dst + k0 + k] += d_packed[l*kz + k]   (IEEE FP32)
+ * for l < n (R for ROWS, C for COLS), k < kz.  Rows of d_dst that the block
+ * does not touch are left unchanged.  Requires 0 <= k0, k0 + kz <= ld_dst. */
+spc3d_status spc3d_scatter_reduce(spc3d_plan plan, spc3d_axis axis, const float* d_packed,
+                                  int32_t kz, float* d_dst, int64_t ld_dst, int32_t k0,
+                                  hipStream_t stream);
+
+/* Move per-entry FP32 values between caller (COO) order and slot order:
+ * CALLER_TO_SLOT: out[p] = in[perm[p]];  SLOT_TO_CALLER: out[perm[p]] = in[p].
+ * in and out must not alias. */
+spc3d_status spc3d_permute_values(spc3d_plan plan, int direction, const float* d_in,
+                                  float* d_out, hipStream_t stream);
+
+/* -------------------------------------------------- graph attention (ext.) */
+
+/* Bytes of scratch spc3d_row_softmax / spc3d_row_softmax_bwd need. */
+spc3d_status spc3d_row_softmax_buffer_size(spc3d_plan plan, size_t* bytes);
+
+/* Row-wise softmax over each row's stored entries (slot order):
+ *   alpha[p] = exp(e[p] - max_row) / sum_{q in row} exp(e[q] - max_row).
+ * Used between the SDDMM scores and the SpMM aggregation of a graph-attention
+ * layer.  d_e and d_alpha hold nnz FP32 values and may alias; d_buf
+ * (256-byte aligned) holds at least spc3d_row_softmax_buffer_size bytes. */
+spc3d_status spc3d_row_softmax(spc3d_plan plan, const float* d_e, float* d_alpha, void* d_buf,
+                               size_t buf_bytes, hipStream_t stream);
+
+/* Backward of spc3d_row_softmax:
+ *   de[p] = alpha[p] * (dalpha[p] - sum_{q in row} alpha[q] * dalpha[q]).
+ * d_de may alias d_dalpha; d_buf as for spc3d_row_softmax. */
+spc3d_status spc3d_row_softmax_bwd(spc3d_plan plan, const float* d_alpha, const float* d_dalpha,
+                                   float* d_de, void* d_buf, size_t buf_bytes,
+                                   hipStream_t stream);
+
+/* ----------------------------------------------------------- diagnostics */
+
+const char* spc3d_status_string(spc3d_status status);
+const char* spc3d_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int spc3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPC3D_H */

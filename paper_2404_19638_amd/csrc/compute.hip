@@ -1,0 +1,565 @@
+// Compute phase: SDDMM, Eq. (1), and SpMM, Eq. (2), over a localized block
+// with a K-slice of width kz (paper: Section "Building 3D SDDMM and SpMM
+// Algorithms", The Compute phase — each of the Z instances forms the inner
+// products over K/Z columns; "Building SpMM" for the row-wise SpMM).
+//
+// Work decomposition (both kernels).  The block's slots are cut into work
+// items of W consecutive slots (W a multiple of 64), one item per wavefront,
+// regardless of row boundaries, so power-law hub rows cannot serialize a
+// wavefront.  A wavefront is split into G = 64 / L groups of L lanes; a group
+// owns one nonzero at a time and each lane of it holds NCH vectors of VEC
+// elements of the kz-wide dense row (16-byte loads: 4 FP32 or 8 bfloat16).
+// Rows are recovered from a 64-bit head bitmap per 64 slots plus the row of
+// the tile's first slot (a popcount), so no per-slot row array is read.
+//
+// SDDMM: in each 64-slot window, group g computes the dots of slots
+// g*L .. g*L+L-1 one after another (lane-parallel FMAs, then an xor-butterfly
+// over the L lanes); lane i ends up holding slot i's dot and the window's 64
+// outputs are written with one coalesced store.
+//
+// SpMM: group g walks a contiguous run of S = W / G slots, accumulating
+// s_p * X[col] in registers; a row that starts and ends inside the run is
+// written directly.  Rows cut by run boundaries leave partial sums in LDS
+// (the first row of a run) or registers (the last); after one barrier the
+// group that started such a row adds the following runs' partials in run
+// order.  Rows cut by item boundaries leave per-item carries that a small
+// second kernel adds in item order (blocked, then a butterfly across groups).
+// The summation order depends only on the structure, so results are
+// deterministic, and every FP32 sum has depth O(S + G + W-items / 16), which
+// keeps the rounding error far inside 1e-5 of the magnitude sum even for rows
+// with 10^5 entries.
+#include "internal.h"
+#include "vec.h"
+
+namespace spc3d {
+
+enum { kLeadNone = 0, kLeadEnds = 1, kLeadThrough = 2 };
+
+// Row of slot s from the head bitmap.
+__device__ inline int row_of(const uint64_t* __restrict__ head, const int32_t* __restrict__ tile_row,
+                             int64_t s) {
+  return tile_row[s >> 6] + __popcll(head[s >> 6] & lanemask_le((int)(s & 63)) & ~1ull);
+}
+
+__device__ inline bool is_head(const uint64_t* __restrict__ head, int64_t s) {
+  return (head[s >> 6] >> (s & 63)) & 1ull;
+}
+
+// ------------------------------------------------------------------ SDDMM
+
+template <typename T, int VEC, int LPN, int NCH>
+__global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int64_t nblocks,
+                                               int wslots, const int32_t* __restrict__ colidx,
+                                               const uint64_t* __restrict__ head,
+                                               const int32_t* __restrict__ tile_row,
+                                               const float* __restrict__ vals,
+                                               const T* __restrict__ A, const T* __restrict__ B,
+                                               int kz, float* __restrict__ out, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPN, q = lane % LPN;
+  const int64_t item = xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;   // uniform per wavefront; no barriers below
+  const int nvec = kz / VEC;
+  const int64_t b = item * wslots;
+  const int64_t e = (b + wslots < nnz) ? b + wslots : nnz;
+  for (int64_t win = b; win < e; win += 64) {
+    const int64_t s = win + lane;
+    const bool valid = s < e;
+    const int col = valid ? colidx[s] : 0;
+    const float v = vals ? (valid ? vals[s] : 0.f) : 1.f;
+    const int row = tile_row[win >> 6] + __popcll(head[win >> 6] & lanemask_le(lane) & ~1ull);
+    float res = 0.f;
+#pragma unroll
+    for (int j = 0; j < LPN; ++j) {
+      const int src = g * LPN + j;
+      const int c = __shfl(col, src);
+      const int r = __shfl(row, src);   // lanes past the end repeat a valid row
+      float acc = 0.f;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int vi = q + ch * LPN;
+        if (vi < nvec) {
+          float a[VEC], bb[VEC];
+          VecLoad<T, VEC>::load(A + (int64_t)r * kz + vi * VEC, a);
+          VecLoad<T, VEC>::load(B + (int64_t)c * kz + vi * VEC, bb);
+#pragma unroll
+          for (int t = 0; t < VEC; ++t) acc = fmaf(a[t], bb[t], acc);
+        }
+      }
+#pragma unroll
+      for (int o = LPN / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+      if (q == j) res = acc;
+    }
+    if (valid) {
+      const float o = v * res;
+      out[s] = accumulate ? out[s] + o : o;
+    }
+  }
+}
+
+// ------------------------------------------------------------------- SpMM
+
+template <int VEC, int NCH>
+__device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int nvec, int q,
+                                 int lpn, const float (&acc)[NCH][VEC], int accumulate) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+      float* y = Y + row * kz + vi * VEC;
+      if constexpr (VEC % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < VEC; t += 4) {
+          float4 o = make_float4(acc[ch][t], acc[ch][t + 1], acc[ch][t + 2], acc[ch][t + 3]);
+          if (accumulate) {
+            const float4 old = *reinterpret_cast<const float4*>(y + t);
+            o.x = old.x + o.x; o.y = old.y + o.y; o.z = old.z + o.z; o.w = old.w + o.w;
+          }
+          *reinterpret_cast<float4*>(y + t) = o;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) y[t] = accumulate ? y[t] + acc[ch][t] : acc[ch][t];
+      }
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void store_vec(float* __restrict__ dst, int nvec, int q, int lpn,
+                                 const float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) dst[vi * VEC + t] = acc[ch][t];
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void add_vec(const float* __restrict__ src, int nvec, int q, int lpn,
+                               float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) acc[ch][t] += src[vi * VEC + t];
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void zero(float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) acc[ch][t] = 0.f;
+}
+
+// LDS bytes one wavefront of k_spmm uses.
+inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec) {
+  const int G = 64 / lpn;
+  return (size_t)wslots * 8 + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4;
+}
+
+template <typename T, int VEC, int LPN, int NCH>
+__global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64_t nblocks,
+                                              int wslots, const int32_t* __restrict__ idx,
+                                              const uint64_t* __restrict__ head,
+                                              const int32_t* __restrict__ tile_row,
+                                              const float* __restrict__ vals,
+                                              const int32_t* __restrict__ vidx,
+                                              const T* __restrict__ X, int kz,
+                                              float* __restrict__ Y, int accumulate,
+                                              float* __restrict__ carry) {
+  constexpr int G = 64 / LPN;
+  constexpr int UB = 8 / NCH;              // slots whose rows are loaded together
+  constexpr int KW = LPN * NCH * VEC;      // padded row width of one group
+  extern __shared__ __align__(16) char smem[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / LPN, q = lane % LPN;
+  char* wbase = smem + (size_t)wv * ((size_t)wslots * 8 + (size_t)G * KW * 4 + (size_t)G * 4);
+  int* s_col = reinterpret_cast<int*>(wbase);
+  float* s_val = reinterpret_cast<float*>(wbase + (size_t)wslots * 4);
+  float* s_lead = reinterpret_cast<float*>(wbase + (size_t)wslots * 8);
+  int* s_kind = reinterpret_cast<int*>(wbase + (size_t)wslots * 8 + (size_t)G * KW * 4);
+
+  const int64_t item = xcd_block(nblocks) * 4 + wv;
+  const bool active = item < nitems;
+  const int nvec = kz / VEC;
+  const int S = wslots / G;
+  int64_t b = 0, e = 0;
+  if (active) {
+    b = item * wslots;
+    e = (b + wslots < nnz) ? b + wslots : nnz;
+    for (int i = lane; i < (int)(e - b); i += 64) {
+      s_col[i] = idx[b + i];
+      s_val[i] = vals ? vals[vidx ? vidx[b + i] : b + i] : 1.f;
+    }
+  }
+  __syncthreads();
+
+  float acc[NCH][VEC];
+  zero(acc);
+  int kind = kLeadNone;
+  bool tail = false, started = false;
+  int cur = 0;
+  const int64_t gs = b + (int64_t)g * S;
+  const int64_t ge = (gs + S < e) ? gs + S : e;
+  if (active && gs < ge) {
+    cur = row_of(head, tile_row, gs);
+    started = is_head(head, gs);
+    for (int64_t s0 = gs; s0 < ge; s0 += UB) {
+      const unsigned hbits = (unsigned)(head[s0 >> 6] >> (s0 & 63)) & ((1u << UB) - 1u);
+      float x[UB][NCH][VEC];
+      float vv[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const bool ok = s0 + u < ge;
+        const int li = ok ? (int)(s0 - b) + u : 0;
+        const int c = s_col[li];
+        vv[u] = ok ? s_val[li] : 0.f;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          const int vi = q + ch * LPN;
+          if (vi < nvec) {
+            VecLoad<T, VEC>::load(X + (int64_t)c * kz + vi * VEC, x[u][ch]);
+          } else {
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) x[u][ch][t] = 0.f;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (s0 + u < ge) {
+          if (s0 + u > gs && ((hbits >> u) & 1u)) {
+            if (started) {
+              store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+            } else {
+              store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
+              kind = kLeadEnds;
+            }
+            zero(acc);
+            ++cur;
+            started = true;
+          }
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) acc[ch][t] = fmaf(vv[u], x[u][ch][t], acc[ch][t]);
+        }
+      }
+    }
+    const bool ends = (ge >= nnz) || is_head(head, ge);
+    if (started) {
+      if (ends)
+        store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+      else
+        tail = true;
+    } else {
+      store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
+      kind = ends ? kLeadEnds : kLeadThrough;
+    }
+  }
+  if (q == 0) s_kind[g] = kind;
+  __syncthreads();
+  if (!active) return;
+
+  if (tail) {
+    bool done = false;
+    for (int g2 = g + 1; g2 < G; ++g2) {
+      const int k = s_kind[g2];
+      if (k == kLeadNone) break;
+      add_vec<VEC, NCH>(s_lead + g2 * KW, nvec, q, LPN, acc);
+      if (k == kLeadEnds) {
+        done = true;
+        break;
+      }
+    }
+    if (done)
+      store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+    else
+      store_vec<VEC, NCH>(carry + (item * 2 + 1) * kz, nvec, q, LPN, acc);
+  }
+  if (g == 0 && s_kind[0] != kLeadNone) {
+    float hc[NCH][VEC];
+    zero(hc);
+    add_vec<VEC, NCH>(s_lead, nvec, q, LPN, hc);
+    if (s_kind[0] == kLeadThrough) {
+      for (int g2 = 1; g2 < G; ++g2) {
+        const int k = s_kind[g2];
+        if (k == kLeadNone) break;
+        add_vec<VEC, NCH>(s_lead + g2 * KW, nvec, q, LPN, hc);
+        if (k == kLeadEnds) break;
+      }
+    }
+    store_vec<VEC, NCH>(carry + (item * 2) * kz, nvec, q, LPN, hc);
+  }
+}
+
+// Rows cut by item boundaries: item j whose last row starts inside it and
+// continues past its end owns the row; it adds its tail carry and the head
+// carries of the items the row runs through, in item order.
+template <int VEC, int LPN, int NCH>
+__global__ __launch_bounds__(256) void k_spmm_fixup(int64_t nnz, int64_t nitems, int wslots,
+                                                    const int32_t* __restrict__ ptr,
+                                                    const uint64_t* __restrict__ head,
+                                                    const int32_t* __restrict__ tile_row, int kz,
+                                                    float* __restrict__ Y, int accumulate,
+                                                    const float* __restrict__ carry) {
+  constexpr int G = 64 / LPN;
+  constexpr int BLK = 16;
+  const int lane = threadIdx.x & 63, g = lane / LPN, q = lane % LPN;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nitems) return;
+  const int64_t b = j * wslots, e = b + wslots;
+  if (e >= nnz || is_head(head, e)) return;
+  const int r = row_of(head, tile_row, e - 1);
+  if (ptr[r] < b) return;
+  const int64_t jl = ((int64_t)ptr[r + 1] - 1) / wslots;
+  const int nvec = kz / VEC;
+  float tot[NCH][VEC];
+  zero(tot);
+  for (int64_t j0 = j + 1 + g; j0 <= jl; j0 += (int64_t)G * BLK) {
+    float blk[NCH][VEC];
+    zero(blk);
+    for (int m = 0; m < BLK; ++m) {
+      const int64_t jj = j0 + (int64_t)m * G;
+      if (jj > jl) break;
+      add_vec<VEC, NCH>(carry + (jj * 2) * kz, nvec, q, LPN, blk);
+    }
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) tot[ch][t] += blk[ch][t];
+  }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) tot[ch][t] += __shfl_xor(tot[ch][t], m * LPN);
+  if (g == 0) {
+    float res[NCH][VEC];
+    zero(res);
+    add_vec<VEC, NCH>(carry + (j * 2 + 1) * kz, nvec, q, LPN, res);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) res[ch][t] += tot[ch][t];
+    store_row<VEC, NCH>(Y, r, kz, nvec, q, LPN, res, accumulate);
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+
+namespace {
+
+struct Shape {
+  int vec;    // elements per 16-byte load (1 = scalar path)
+  int lanes;  // L
+  int nch;    // vectors per lane
+  int items;  // W
+};
+
+int pow2ceil(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, bool spmm, Shape* sh) {
+  const int vfull = (t == SPC3D_F32) ? 4 : 8;
+  sh->vec = (vec_ok && kz % vfull == 0) ? vfull : 1;
+  if (sh->vec == 1 && kz > kMaxKzScalar)
+    return fail(SPC3D_ERR_UNSUPPORTED, "kz=%d needs 16-byte aligned rows with kz %% %d == 0", kz,
+                vfull);
+  const int nvec = kz / sh->vec;
+  if (variant < 0) {
+    sh->lanes = pow2ceil(nvec);
+    if (sh->lanes > 16) sh->lanes = 16;
+    if (sh->lanes < 2) sh->lanes = 2;
+    while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
+    sh->items = 256;
+  } else {
+    const int lg = variant & 15, lw = (variant >> 4) & 15;
+    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 8))
+      return fail(SPC3D_ERR_INVALID_ARG, "bad variant %d", variant);
+    sh->lanes = 1 << lg;
+    sh->items = 64 << lw;
+  }
+  sh->nch = (nvec + sh->lanes - 1) / sh->lanes;
+  if (sh->nch == 3) sh->nch = 4;
+  if (sh->nch > 4)
+    return fail(SPC3D_ERR_UNSUPPORTED, "variant has too few lanes for kz=%d", kz);
+  if (spmm) {
+    const int G = 64 / sh->lanes;
+    if (sh->items / G < 8)
+      return fail(SPC3D_ERR_UNSUPPORTED, "SpMM variant needs >= 8 slots per group");
+  }
+  return SPC3D_OK;
+}
+
+#define SPC3D_SWITCH_NCH(NCHV, ...)                     \
+  switch (NCHV) {                                       \
+    case 1: { constexpr int NCH_ = 1; __VA_ARGS__; break; } \
+    case 2: { constexpr int NCH_ = 2; __VA_ARGS__; break; } \
+    default: { constexpr int NCH_ = 4; __VA_ARGS__; break; } \
+  }
+
+#define SPC3D_SWITCH_LPN(LPNV, ...)                      \
+  switch (LPNV) {                                        \
+    case 2: { constexpr int LPN_ = 2; __VA_ARGS__; break; }  \
+    case 4: { constexpr int LPN_ = 4; __VA_ARGS__; break; }  \
+    case 8: { constexpr int LPN_ = 8; __VA_ARGS__; break; }  \
+    case 16: { constexpr int LPN_ = 16; __VA_ARGS__; break; } \
+    case 32: { constexpr int LPN_ = 32; __VA_ARGS__; break; } \
+    default: { constexpr int LPN_ = 64; __VA_ARGS__; break; } \
+  }
+
+template <typename T, int VEC>
+void launch_sddmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
+                  const Orient& o, const float* vals, const void* A, const void* B, int kz,
+                  float* out, int accumulate) {
+  SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
+      hipLaunchKernelGGL((k_sddmm<T, VEC, LPN_, NCH_>), dim3((unsigned)nblocks), dim3(256), 0,
+                         st, nnz, nitems, nblocks, sh.items, o.idx, o.head, o.tile_row, vals,
+                         static_cast<const T*>(A), static_cast<const T*>(B), kz, out,
+                         accumulate)));
+}
+
+template <typename T, int VEC>
+void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
+                 const Orient& o, const float* vals, const void* X, int kz, float* Y,
+                 int accumulate, float* carry, size_t lds) {
+  SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
+      hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_>), dim3((unsigned)nblocks), dim3(256), lds,
+                         st, nnz, nitems, nblocks, sh.items, o.idx, o.head, o.tile_row, vals,
+                         o.vidx, static_cast<const T*>(X), kz, Y, accumulate, carry);
+      hipLaunchKernelGGL((k_spmm_fixup<VEC, LPN_, NCH_>),
+                         dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, st, nnz, nitems,
+                         sh.items, o.ptr, o.head, o.tile_row, kz, Y, accumulate, carry)));
+}
+
+}  // namespace
+}  // namespace spc3d
+
+using namespace spc3d;
+
+extern "C" {
+
+spc3d_status spc3d_sddmm(spc3d_plan h, const float* d_vals, const void* d_A, const void* d_B,
+                         spc3d_dtype ab_t, int32_t kz, float* d_out, int mode, int variant,
+                         hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
+  if (mode != SPC3D_OVERWRITE && mode != SPC3D_ACCUMULATE)
+    return fail(SPC3D_ERR_INVALID_ARG, "bad mode");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_A || !d_B || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  Shape sh;
+  st = pick_shape(kz, ab_t, aligned16(d_A) && aligned16(d_B), variant, false, &sh);
+  if (st != SPC3D_OK) return st;
+  st = use_device(p);
+  if (st != SPC3D_OK) return st;
+  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
+  const int64_t nblocks = (nitems + 3) / 4;
+  const Orient o = p->csr();
+  const int acc = mode == SPC3D_ACCUMULATE;
+  if (ab_t == SPC3D_F32) {
+    if (sh.vec == 4)
+      launch_sddmm<float, 4>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_A, d_B, kz, d_out,
+                             acc);
+    else
+      launch_sddmm<float, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_A, d_B, kz, d_out,
+                             acc);
+  } else {
+    if (sh.vec == 8)
+      launch_sddmm<bf16_t, 8>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_A, d_B, kz,
+                              d_out, acc);
+    else
+      launch_sddmm<bf16_t, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_A, d_B, kz,
+                              d_out, acc);
+  }
+  SPC3D_LAUNCHED("sddmm");
+  return SPC3D_OK;
+}
+
+spc3d_status spc3d_spmm_buffer_size(spc3d_plan h, int transpose, int32_t kz, int variant,
+                                    size_t* bytes) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (!bytes) return fail(SPC3D_ERR_INVALID_ARG, "bytes is NULL");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  Shape sh;
+  // The buffer does not depend on the element type or alignment.
+  st = pick_shape(kz, SPC3D_F32, true, variant, true, &sh);
+  if (st != SPC3D_OK && variant >= 0) {
+    st = pick_shape(kz, SPC3D_F32, false, variant, true, &sh);
+    if (st != SPC3D_OK) return st;
+  }
+  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
+  *bytes = (size_t)(nitems > 0 ? nitems : 1) * 2 * (size_t)kz * 4;
+  return SPC3D_OK;
+}
+
+spc3d_status spc3d_spmm(spc3d_plan h, int transpose, const float* d_vals, const void* d_X,
+                        spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant,
+                        void* d_buf, size_t buf_bytes, hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (transpose != 0 && transpose != 1) return fail(SPC3D_ERR_INVALID_ARG, "bad transpose");
+  if (transpose && !(p->flags & SPC3D_BUILD_CSC))
+    return fail(SPC3D_ERR_INVALID_ARG, "transposed SpMM needs a plan built with BUILD_CSC");
+  if (x_t != SPC3D_F32 && x_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad x_t");
+  if (mode != SPC3D_OVERWRITE && mode != SPC3D_ACCUMULATE)
+    return fail(SPC3D_ERR_INVALID_ARG, "bad mode");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_X || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
+    return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
+  Shape sh;
+  st = pick_shape(kz, x_t, aligned16(d_X) && aligned16(d_Y), variant, true, &sh);
+  if (st != SPC3D_OK) return st;
+  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
+  if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
+    return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes,
+                (size_t)nitems * 2 * (size_t)kz * 4);
+  const size_t lds = 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec);
+  if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
+  st = use_device(p);
+  if (st != SPC3D_OK) return st;
+  const int64_t nblocks = (nitems + 3) / 4;
+  const Orient o = transpose ? p->csc() : p->csr();
+  const int acc = mode == SPC3D_ACCUMULATE;
+  float* carry = static_cast<float*>(d_buf);
+  if (x_t == SPC3D_F32) {
+    if (sh.vec == 4)
+      launch_spmm<float, 4>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
+                            carry, lds);
+    else
+      launch_spmm<float, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
+                            carry, lds);
+  } else {
+    if (sh.vec == 8)
+      launch_spmm<bf16_t, 8>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
+                             carry, lds);
+    else
+      launch_spmm<bf16_t, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
+                             carry, lds);
+  }
+  SPC3D_LAUNCHED("spmm");
+  return SPC3D_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,310 @@
+"""Python binding of the spc3d C ABI (``include/spc3d.h``).
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name (without the ``spc3d_`` prefix); PyTorch provides device memory
+(tensors) and the HIP stream (``torch.cuda.current_stream()``).  There is no
+fallback: if ``libspc3d.so`` is missing or a call fails, an exception is
+raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspc3d.so")
+
+OK, ERR_INVALID_ARG, ERR_OUT_OF_RANGE, ERR_WORKSPACE, ERR_UNSUPPORTED, ERR_HIP, ERR_BAD_HANDLE = range(7)
+F32, BF16 = 0, 1
+ROWS, COLS = 0, 1
+OVERWRITE, ACCUMULATE = 0, 1
+BUILD_CSC = 1
+CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
+
+
+def variant(lg_lanes: int, lg_items: int) -> int:
+    """SPC3D_VARIANT: 2^lg_lanes lanes per nonzero, 64 * 2^lg_items slots per item."""
+    return lg_lanes | (lg_items << 4)
+
+
+class Spc3dError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        super().__init__(f"{func} failed with status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libspc3d.so (built in-tree by ``build.py``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2404_19638_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    sigs = {
+        "spc3d_plan_workspace_size": [i64, i64, i64, i64, i64, u32, P(sz)],
+        "spc3d_plan_create_coo": [P(vp), i64, vp, vp, i64, i64, i64, i64, u32, vp, sz, vp],
+        "spc3d_plan_query": [vp, P(i64), P(i64), P(i64)],
+        "spc3d_plan_maps": [vp, vp],
+        "spc3d_plan_destroy": [vp],
+        "spc3d_gather": [vp, ctypes.c_int, vp, ctypes.c_int, i64, i32, i32, vp, ctypes.c_int, vp],
+        "spc3d_sddmm": [vp, vp, vp, vp, ctypes.c_int, i32, vp, ctypes.c_int, ctypes.c_int, vp],
+        "spc3d_spmm_buffer_size": [vp, ctypes.c_int, i32, ctypes.c_int, P(sz)],
+        "spc3d_spmm": [vp, ctypes.c_int, vp, vp, ctypes.c_int, i32, vp, ctypes.c_int, ctypes.c_int,
+                       vp, sz, vp],
+        "spc3d_scatter_reduce": [vp, ctypes.c_int, vp, i32, vp, i64, i32, vp],
+        "spc3d_permute_values": [vp, ctypes.c_int, vp, vp, vp],
+        "spc3d_row_softmax_buffer_size": [vp, P(sz)],
+        "spc3d_row_softmax": [vp, vp, vp, vp, sz, vp],
+        "spc3d_row_softmax_bwd": [vp, vp, vp, vp, vp, sz, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.spc3d_status_string.argtypes = [ctypes.c_int]
+    L.spc3d_status_string.restype = ctypes.c_char_p
+    L.spc3d_last_error.argtypes = []
+    L.spc3d_last_error.restype = ctypes.c_char_p
+    L.spc3d_version.argtypes = []
+    L.spc3d_version.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, func: str):
+    if status != OK:
+        raise Spc3dError(status, func, lib().spc3d_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(cond: bool, msg: str):
+    """Host-side shape check before a launch (the C ABI cannot see tensor sizes)."""
+    if not cond:
+        raise ValueError(msg)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class _Maps(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("gmap_r", "gmap_c", "lmap_r", "lmap_c", "rowptr",
+                                                "colidx", "perm", "colptr", "rowidx_t", "slot_t")]
+
+
+class Plan:
+    """A localized block living in a caller-owned workspace tensor."""
+
+    def __init__(self, handle, ws: torch.Tensor, row_range, col_range, flags):
+        self.handle = handle
+        self.ws = ws
+        self.row_range = tuple(int(x) for x in row_range)
+        self.col_range = tuple(int(x) for x in col_range)
+        self.flags = flags
+        R, C, nnz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().spc3d_plan_query(handle, ctypes.byref(R), ctypes.byref(C), ctypes.byref(nnz)),
+               "spc3d_plan_query")
+        self.R, self.C, self.nnz = R.value, C.value, nnz.value
+        self._bufs = {}
+
+    def _view(self, addr, n, dtype):
+        if addr is None or n == 0:
+            return torch.empty(0, dtype=dtype, device=self.ws.device)
+        off = addr - self.ws.data_ptr()
+        nbytes = n * torch.empty(0, dtype=dtype).element_size()
+        return self.ws[off:off + nbytes].view(dtype)
+
+    def maps(self) -> dict:
+        """Device views of gmap/lmap/rowptr/colidx/perm (and the CSC arrays)."""
+        m = _Maps()
+        _check(lib().spc3d_plan_maps(self.handle, ctypes.byref(m)), "spc3d_plan_maps")
+        rr = self.row_range[1] - self.row_range[0]
+        cr = self.col_range[1] - self.col_range[0]
+        out = dict(gmap_r=self._view(m.gmap_r, self.R, torch.int64),
+                   gmap_c=self._view(m.gmap_c, self.C, torch.int64),
+                   lmap_r=self._view(m.lmap_r, rr, torch.int32),
+                   lmap_c=self._view(m.lmap_c, cr, torch.int32),
+                   rowptr=self._view(m.rowptr, self.R + 1, torch.int32),
+                   colidx=self._view(m.colidx, self.nnz, torch.int32),
+                   perm=self._view(m.perm, self.nnz, torch.int32))
+        if m.colptr:
+            out.update(colptr=self._view(m.colptr, self.C + 1, torch.int32),
+                       rowidx_t=self._view(m.rowidx_t, self.nnz, torch.int32),
+                       slot_t=self._view(m.slot_t, self.nnz, torch.int32))
+        return out
+
+    def buffer(self, key, nbytes):
+        """Cached 256-byte aligned scratch tensor (torch allocations are aligned)."""
+        b = self._bufs.get(key)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.ws.device)
+            self._bufs[key] = b
+        return b
+
+    def __del__(self):
+        try:
+            if self.handle is not None and _lib is not None:
+                _lib.spc3d_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------- setup
+
+def plan_workspace_size(nnz, row_lo, row_hi, col_lo, col_hi, flags=0) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_plan_workspace_size(nnz, row_lo, row_hi, col_lo, col_hi, flags,
+                                           ctypes.byref(b)), "spc3d_plan_workspace_size")
+    return b.value
+
+
+def plan_create_coo(row_gid: torch.Tensor, col_gid: torch.Tensor, row_range, col_range,
+                    flags: int = 0, ws: torch.Tensor | None = None, stream=None) -> Plan:
+    """Localize a COO block of int64 global ids (device tensors).  Synchronizes."""
+    assert row_gid.dtype == torch.int64 and col_gid.dtype == torch.int64
+    assert row_gid.is_contiguous() and col_gid.is_contiguous()
+    nnz = row_gid.numel()
+    need = plan_workspace_size(nnz, row_range[0], row_range[1], col_range[0], col_range[1], flags)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=row_gid.device)
+    h = ctypes.c_void_p()
+    _check(lib().spc3d_plan_create_coo(ctypes.byref(h), nnz, _ptr(row_gid), _ptr(col_gid),
+                                       row_range[0], row_range[1], col_range[0], col_range[1],
+                                       flags, _ptr(ws), ws.numel(), _stream(stream)),
+           "spc3d_plan_create_coo")
+    return Plan(h, ws, row_range, col_range, flags)
+
+
+# ------------------------------------------------------------------ hot path
+
+def gather(plan: Plan, axis: int, src: torch.Tensor, k0: int, kz: int,
+           packed_dtype=torch.float32, out: torch.Tensor | None = None, stream=None):
+    n = plan.R if axis == ROWS else plan.C
+    rng = plan.row_range if axis == ROWS else plan.col_range
+    if out is None:
+        out = torch.empty((n, kz), dtype=packed_dtype, device=src.device)
+    _need(src.dim() == 2 and src.stride(1) == 1, "src must be a row-major 2-D tensor")
+    _need(src.shape[0] >= rng[1] - rng[0], "src needs one row per id of the axis range")
+    _need(out.is_contiguous() and out.numel() >= n * kz, "packed output too small")
+    _check(lib().spc3d_gather(plan.handle, axis, _ptr(src), _dtype_code(src), src.stride(0), k0,
+                              kz, _ptr(out), _dtype_code(out), _stream(stream)), "spc3d_gather")
+    return out
+
+
+def sddmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | None = None,
+          out: torch.Tensor | None = None, mode: int = OVERWRITE, variant: int = -1, stream=None):
+    kz = A.shape[1] if kz is None else kz
+    _need(A.dtype == B.dtype, "A and B must share a dtype")
+    _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
+    _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
+          "vals must hold nnz FP32 values")
+    if out is None:
+        out = torch.empty(plan.nnz, dtype=torch.float32, device=A.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
+          "out must hold nnz FP32 values")
+    _check(lib().spc3d_sddmm(plan.handle, _ptr(vals), _ptr(A), _ptr(B), _dtype_code(A), kz,
+                             _ptr(out), mode, variant, _stream(stream)), "spc3d_sddmm")
+    return out
+
+
+def spmm_buffer_size(plan: Plan, transpose: int, kz: int, variant: int = -1) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_spmm_buffer_size(plan.handle, transpose, kz, variant, ctypes.byref(b)),
+           "spc3d_spmm_buffer_size")
+    return b.value
+
+
+def spmm(plan: Plan, vals, X: torch.Tensor, transpose: int = 0, kz: int | None = None,
+         out: torch.Tensor | None = None, mode: int = OVERWRITE, variant: int = -1,
+         buf: torch.Tensor | None = None, stream=None):
+    kz = X.shape[1] if kz is None else kz
+    n = plan.C if transpose else plan.R
+    nx = plan.R if transpose else plan.C
+    _need(X.is_contiguous() and X.numel() >= nx * kz, "X too small for kz")
+    _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
+          "vals must hold nnz FP32 values")
+    if out is None:
+        out = torch.empty((n, kz), dtype=torch.float32, device=X.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n * kz,
+          "out too small")
+    need = spmm_buffer_size(plan, transpose, kz, variant)
+    if buf is None:
+        buf = plan.buffer(("spmm", transpose), need)
+    _check(lib().spc3d_spmm(plan.handle, transpose, _ptr(vals), _ptr(X), _dtype_code(X), kz,
+                            _ptr(out), mode, variant, _ptr(buf), buf.numel(), _stream(stream)),
+           "spc3d_spmm")
+    return out
+
+
+def scatter_reduce(plan: Plan, axis: int, packed: torch.Tensor, dst: torch.Tensor, k0: int,
+                   stream=None):
+    n = plan.R if axis == ROWS else plan.C
+    rng = plan.row_range if axis == ROWS else plan.col_range
+    _need(dst.dim() == 2 and dst.stride(1) == 1 and dst.dtype == torch.float32,
+          "dst must be a row-major FP32 2-D tensor")
+    _need(dst.shape[0] >= rng[1] - rng[0], "dst needs one row per id of the axis range")
+    _need(packed.dtype == torch.float32 and packed.is_contiguous() and packed.dim() == 2
+          and packed.shape[0] >= n, "packed must be [n, kz] FP32")
+    _check(lib().spc3d_scatter_reduce(plan.handle, axis, _ptr(packed), packed.shape[1],
+                                      _ptr(dst), dst.stride(0), k0, _stream(stream)),
+           "spc3d_scatter_reduce")
+    return dst
+
+
+def permute_values(plan: Plan, direction: int, x: torch.Tensor, out=None, stream=None):
+    _need(x.dtype == torch.float32 and x.is_contiguous() and x.numel() >= plan.nnz,
+          "x must hold nnz FP32 values")
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().spc3d_permute_values(plan.handle, direction, _ptr(x), _ptr(out),
+                                      _stream(stream)), "spc3d_permute_values")
+    return out
+
+
+def row_softmax_buffer_size(plan: Plan) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_row_softmax_buffer_size(plan.handle, ctypes.byref(b)),
+           "spc3d_row_softmax_buffer_size")
+    return b.value
+
+
+def row_softmax(plan: Plan, e: torch.Tensor, out=None, stream=None):
+    _need(e.dtype == torch.float32 and e.is_contiguous() and e.numel() >= plan.nnz,
+          "e must hold nnz FP32 values")
+    out = torch.empty_like(e) if out is None else out
+    buf = plan.buffer("softmax", row_softmax_buffer_size(plan))
+    _check(lib().spc3d_row_softmax(plan.handle, _ptr(e), _ptr(out), _ptr(buf), buf.numel(),
+                                   _stream(stream)), "spc3d_row_softmax")
+    return out
+
+
+def row_softmax_bwd(plan: Plan, alpha: torch.Tensor, dalpha: torch.Tensor, out=None, stream=None):
+    _need(alpha.numel() >= plan.nnz and dalpha.numel() >= plan.nnz, "need nnz values")
+    out = torch.empty_like(alpha) if out is None else out
+    buf = plan.buffer("softmax", row_softmax_buffer_size(plan))
+    _check(lib().spc3d_row_softmax_bwd(plan.handle, _ptr(alpha), _ptr(dalpha), _ptr(out),
+                                       _ptr(buf), buf.numel(), _stream(stream)),
+           "spc3d_row_softmax_bwd")
+    return out

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Integer and data-movement results must match bit for bit; FP32 results must
+lie within 1e-5 of the oracle's magnitude sum M elementwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_19638_amd import synth
+from helpers import assert_within_mag
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():   # pragma: no cover - collected on CPU hosts too
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="no GPU")]
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _spc():
+    from paper_2404_19638_amd import spc3d
+    return spc3d
+
+
+def _upload(p):
+    rows = torch.from_numpy(p.rows).to(DEV)
+    cols = torch.from_numpy(p.cols).to(DEV)
+    return rows, cols
+
+
+def _plan(p, flags=0):
+    spc = _spc()
+    rows, cols = _upload(p)
+    return spc.plan_create_coo(rows, cols, p.row_range, p.col_range, flags)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _check_relabel(plan, ref, csc):
+    m = plan.maps()
+    assert plan.R == ref["R"] and plan.C == ref["C"]
+    keys = ["gmap_r", "gmap_c", "lmap_r", "lmap_c", "rowptr", "colidx", "perm"]
+    if csc:
+        keys += ["colptr", "rowidx_t", "slot_t"]
+    for k in keys:
+        np.testing.assert_array_equal(_np(m[k]), ref[k], err_msg=k)
+
+
+def _problems():
+    g = synth.small_rmat(12, 6, 32, 31, row_range=(1 << 11, 1 << 12), col_range=(0, 1 << 11))
+    return {
+        "tiny": synth.tiny(),
+        "rmat12": g,
+    }
+
+
+# ----------------------------------------------------------------- relabel
+
+@pytest.mark.parametrize("name", ["tiny", "rmat12"])
+def test_relabel_bit_exact(name):
+    p = _problems()[name]
+    _say(f"relabel {name} nnz={p.nnz}")
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = _plan(p, _spc().BUILD_CSC)
+    _check_relabel(plan, ref, True)
+
+
+def test_relabel_edge_cases():
+    spc = _spc()
+    cases = [
+        ("single", np.array([7]), np.array([3]), (0, 10), (0, 5)),
+        ("dups", np.array([2, 2, 2, 5, 2]), np.array([1, 1, 4, 1, 1]), (0, 8), (0, 8)),
+        ("one_row", np.full(300, 4), np.arange(300) % 97, (4, 5), (0, 97)),
+        ("one_col", np.arange(200), np.zeros(200, np.int64), (0, 200), (0, 1)),
+        ("ragged", np.arange(129) * 3 % 61, np.arange(129) * 7 % 53, (0, 61), (0, 53)),
+    ]
+    for name, r, c, rr, cr in cases:
+        _say(f"relabel edge {name}")
+        r = r.astype(np.int64)
+        c = c.astype(np.int64)
+        ref = oracle.relabel(r, c, rr, cr, csc=True)
+        plan = spc.plan_create_coo(torch.from_numpy(r).to(DEV), torch.from_numpy(c).to(DEV), rr,
+                                   cr, spc.BUILD_CSC)
+        _check_relabel(plan, ref, True)
+
+
+def test_relabel_empty_block():
+    spc = _spc()
+    e = torch.zeros(0, dtype=torch.int64, device=DEV)
+    plan = spc.plan_create_coo(e, e, (0, 100), (50, 60), spc.BUILD_CSC)
+    assert (plan.R, plan.C, plan.nnz) == (0, 0, 0)
+    m = plan.maps()
+    assert (_np(m["lmap_r"]) == -1).all() and (_np(m["lmap_c"]) == -1).all()
+    np.testing.assert_array_equal(_np(m["rowptr"]), [0])
+    # hot calls on an empty block are no-ops
+    A = torch.zeros((0, 8), device=DEV)
+    assert spc.sddmm(plan, None, A, A, 8).numel() == 0
+    assert spc.spmm(plan, None, A, 0, 8).numel() == 0
+
+
+def test_relabel_out_of_range_is_an_error():
+    spc = _spc()
+    r = torch.tensor([1, 2, 30], dtype=torch.int64, device=DEV)
+    c = torch.tensor([0, 1, 2], dtype=torch.int64, device=DEV)
+    with pytest.raises(spc.Spc3dError) as ei:
+        spc.plan_create_coo(r, c, (0, 10), (0, 10))
+    assert ei.value.status == spc.ERR_OUT_OF_RANGE
+
+
+# ------------------------------------------------------- gather / scatter
+
+@pytest.mark.parametrize("name", ["tiny", "rmat12"])
+def test_gather_scatter_bit_exact(name):
+    spc = _spc()
+    p = _problems()[name]
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range)
+    plan = _plan(p)
+    A = torch.from_numpy(p.A_src).to(DEV)
+    B = torch.from_numpy(p.B_src).to(DEV)
+    for (k0, kz) in [(0, p.K), (4, 8), (1, 3)]:
+        _say(f"gather {name} k0={k0} kz={kz}")
+        ga = spc.gather(plan, spc.ROWS, A, k0, kz)
+        gb = spc.gather(plan, spc.COLS, B, k0, kz)
+        np.testing.assert_array_equal(_np(ga), oracle.gather_f32(ref["gmap_r"], p.row_range[0],
+                                                                 p.A_src, k0, kz))
+        np.testing.assert_array_equal(_np(gb), oracle.gather_f32(ref["gmap_c"], p.col_range[0],
+                                                                 p.B_src, k0, kz))
+        if kz % 8 == 0:
+            hb = spc.gather(plan, spc.ROWS, A, k0, kz, torch.bfloat16)
+            np.testing.assert_array_equal(_np(hb.view(torch.int16)).view(np.uint16),
+                                          oracle.gather_bf16(ref["gmap_r"], p.row_range[0],
+                                                             p.A_src, k0, kz))
+        # scatter-reduce: one IEEE FP32 add per element, bit-exact
+        Yloc = torch.randn((plan.R, kz), device=DEV)
+        dst = torch.randn(p.A_src.shape, device=DEV)
+        want = _np(dst).copy()
+        oracle.scatter_add_f32(ref["gmap_r"], p.row_range[0], _np(Yloc), want, k0)
+        spc.scatter_reduce(plan, spc.ROWS, Yloc, dst, k0)
+        np.testing.assert_array_equal(_np(dst).view(np.uint32), want.view(np.uint32))
+
+
+def test_bf16_conversion_over_bit_patterns():
+    """Gather-convert of 2^26 strided FP32 patterns (all classes) vs the oracle."""
+    spc = _spc()
+    n = 1 << 20
+    kz = 64
+    pats = (np.arange(n * kz, dtype=np.uint64) * 64 + 17).astype(np.uint32)
+    pats[:4096] = np.arange(4096, dtype=np.uint32) | 0x7F800000   # inf/NaN payloads
+    pats[4096:8192] = np.arange(4096, dtype=np.uint32) | 0xFF7FF000  # near -max
+    src = pats.view(np.float32).reshape(n, kz)
+    ids = np.arange(n, dtype=np.int64)
+    plan = spc.plan_create_coo(torch.from_numpy(ids).to(DEV), torch.from_numpy(ids).to(DEV),
+                               (0, n), (0, n))
+    got = spc.gather(plan, spc.ROWS, torch.from_numpy(src).to(DEV), 0, kz, torch.bfloat16)
+    want = oracle.bf16_rne(src)
+    np.testing.assert_array_equal(_np(got.view(torch.int16)).view(np.uint16), want)
+
+
+# ------------------------------------------------------------ SDDMM / SpMM
+
+def _local_inputs(p, ref, k0, kz, dtype=np.float32):
+    Aloc = oracle.gather_f32(ref["gmap_r"], p.row_range[0], p.A_src, k0, kz)
+    Bloc = oracle.gather_f32(ref["gmap_c"], p.col_range[0], p.B_src, k0, kz)
+    return Aloc, Bloc
+
+
+VARIANTS = [-1, (1, 2), (2, 1), (3, 0), (3, 2), (3, 4), (4, 2), (5, 3), (6, 4)]
+
+
+def _variant(spc, v):
+    return v if isinstance(v, int) else spc.variant(*v)
+
+
+@pytest.mark.parametrize("name", ["tiny", "rmat12"])
+@pytest.mark.parametrize("kz", [32, 16, 8, 3, 1])
+def test_sddmm_spmm_parity(name, kz):
+    spc = _spc()
+    p = _problems()[name]
+    k0 = 0 if kz > 8 else 5
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = _plan(p, spc.BUILD_CSC)
+    Aloc, Bloc = _local_inputs(p, ref, k0, kz)
+    o_sd, m_sd = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, p.A_src,
+                              p.B_src, k0, kz)
+    o_sd, m_sd = o_sd[ref["perm"]], m_sd[ref["perm"]]
+    o_sp, m_sp = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"],
+                             ref["R"], p.vals, p.B_src, k0, kz)
+    # transposed SpMM = SpMM of the transposed block
+    o_spt, m_spt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"],
+                               ref["C"], p.vals, p.A_src, k0, kz)
+    vals_slot = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    A = torch.from_numpy(Aloc).to(DEV)
+    B = torch.from_numpy(Bloc).to(DEV)
+    for v in VARIANTS:
+        vv = _variant(spc, v)
+        _say(f"sddmm/spmm {name} kz={kz} variant={v}")
+        try:
+            out = spc.sddmm(plan, vals_slot, A, B, kz, variant=vv)
+        except spc.Spc3dError as e:
+            assert e.status == spc.ERR_UNSUPPORTED, e
+            continue
+        assert_within_mag(_np(out), o_sd, m_sd, what=f"sddmm v={v}")
+        try:
+            Y = spc.spmm(plan, vals_slot, B, 0, kz, variant=vv)
+        except spc.Spc3dError as e:
+            assert e.status == spc.ERR_UNSUPPORTED, e
+            continue
+        assert_within_mag(_np(Y), o_sp, m_sp, what=f"spmm v={v}")
+        YT = spc.spmm(plan, vals_slot, A, 1, kz, variant=vv)
+        assert_within_mag(_np(YT), o_spt, m_spt, what=f"spmm^T v={v}")
+
+
+def test_pattern_only_and_accumulate_modes():
+    spc = _spc()
+    p = _problems()["rmat12"]
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range)
+    plan = _plan(p)
+    K = p.K
+    # Z = 4 K-slices accumulated in slice order equal the full-K result
+    out = torch.zeros(plan.nnz, device=DEV)
+    A = torch.from_numpy(p.A_src).to(DEV)
+    B = torch.from_numpy(p.B_src).to(DEV)
+    vals = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    Y = torch.zeros((plan.R, K), device=DEV)
+    for z in range(4):
+        kz = K // 4
+        al = spc.gather(plan, spc.ROWS, A, z * kz, kz)
+        bl = spc.gather(plan, spc.COLS, B, z * kz, kz)
+        spc.sddmm(plan, vals, al, bl, kz, out=out, mode=spc.ACCUMULATE)
+        yz = spc.spmm(plan, vals, bl, 0, kz)
+        Y[:, z * kz:(z + 1) * kz] = yz
+    o, m = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, p.A_src, p.B_src,
+                        0, K)
+    assert_within_mag(_np(out), o[ref["perm"]], m[ref["perm"]], what="Z-sum sddmm")
+    # pattern-only sampling (s == 1) and accumulate for SpMM
+    o1, m1 = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], None, p.A_src, p.B_src,
+                          0, K)
+    al = spc.gather(plan, spc.ROWS, A, 0, K)
+    bl = spc.gather(plan, spc.COLS, B, 0, K)
+    assert_within_mag(_np(spc.sddmm(plan, None, al, bl, K)), o1[ref["perm"]], m1[ref["perm"]],
+                      what="pattern sddmm")
+    Y2 = spc.spmm(plan, vals, bl, 0, K)
+    spc.spmm(plan, vals, bl, 0, K, out=Y2, mode=spc.ACCUMULATE)
+    ys, ms = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"], ref["R"],
+                         p.vals, p.B_src, 0, K)
+    assert_within_mag(_np(Y2), 2 * ys, 2 * ms, what="spmm accumulate")
+
+
+def test_determinism_and_permute():
+    spc = _spc()
+    p = _problems()["rmat12"]
+    plan = _plan(p)
+    vals = torch.from_numpy(p.vals).to(DEV)
+    slot = spc.permute_values(plan, spc.CALLER_TO_SLOT, vals)
+    back = spc.permute_values(plan, spc.SLOT_TO_CALLER, slot)
+    assert torch.equal(back, vals)
+    perm = _np(plan.maps()["perm"])
+    np.testing.assert_array_equal(_np(slot), p.vals[perm])
+    A = spc.gather(plan, spc.ROWS, torch.from_numpy(p.A_src).to(DEV), 0, 16)
+    B = spc.gather(plan, spc.COLS, torch.from_numpy(p.B_src).to(DEV), 0, 16)
+    o1 = spc.sddmm(plan, slot, A, B)
+    o2 = spc.sddmm(plan, slot, A, B)
+    y1 = spc.spmm(plan, slot, B)
+    y2 = spc.spmm(plan, slot, B)
+    assert torch.equal(o1, o2) and torch.equal(y1, y2)
+
+
+def test_bad_arguments_are_rejected():
+    spc = _spc()
+    p = _problems()["tiny"]
+    plan = _plan(p)
+    A = torch.zeros((plan.R, 32), device=DEV)
+    B = torch.zeros((plan.C, 32), device=DEV)
+    with pytest.raises(spc.Spc3dError) as ei:
+        spc.sddmm(plan, None, A, B, 32, variant=0x7)
+    assert ei.value.status == spc.ERR_INVALID_ARG
+    with pytest.raises(spc.Spc3dError) as ei:
+        spc.spmm(plan, None, A, 1, 32)   # no CSC in this plan
+    assert ei.value.status == spc.ERR_INVALID_ARG
+    with pytest.raises(spc.Spc3dError) as ei:
+        spc.gather(plan, spc.ROWS, torch.zeros((4096, 8), device=DEV), 4, 8)
+    assert ei.value.status == spc.ERR_INVALID_ARG
