@@ -48,6 +48,8 @@ def algorithmic_bytes(R, C, nnz, kz, b):
         "sddmm": 4 * (R + 1) + 12 * nnz + kz * b * (R + C),
         "spmm": 4 * (R + 1) + 8 * nnz + kz * b * C + 4 * kz * R,
         "scatter": 8 * R + 12 * kz * R,
+        # one pass: S structure, values and B rows read once for both products
+        "sddmm_spmm": 4 * (R + 1) + 12 * nnz + kz * b * (R + C) + 4 * kz * R,
     }
 
 
@@ -104,6 +106,10 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2405)
+    ap.add_argument("--fused", type=int, default=1,
+                    help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path would shard one "
@@ -118,6 +124,14 @@ def main():
     from paper_2404_19638_amd import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 18
+        a = torch.ones(n, device=dev)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
     t0 = time.perf_counter()
     p = synth.share3d(seed=args.seed)
     log(f"bench: generated share3d block nnz={p.nnz} in {time.perf_counter() - t0:.1f} s")
@@ -146,7 +160,10 @@ def main():
     Y_loc = torch.empty((R, kz), device=dev)
     spbuf = torch.empty(spc.spmm_buffer_size(plan, 0, kz, args.variant), dtype=torch.uint8,
                         device=dev)
-    names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
+    if args.fused:
+        names = ["gather_A", "gather_B", "sddmm_spmm", "scatter"]
+    else:
+        names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
 
     def step(ev=None):
         def mark(i):
@@ -157,16 +174,22 @@ def main():
         mark(1)
         spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
         mark(2)
-        spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=args.variant)
-        mark(3)
-        spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=args.variant, buf=spbuf)
-        mark(4)
+        if args.fused:
+            spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=args.variant,
+                           buf=spbuf)
+            mark(3)
+        else:
+            spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=args.variant)
+            mark(3)
+            spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=args.variant, buf=spbuf)
+            mark(4)
         spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
-        mark(5)
+        mark(len(names))
 
     for _ in range(args.warmup):
         step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+              for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -180,7 +203,7 @@ def main():
     flops = 4.0 * kz * nnz
     value = flops / (ms_per_step * 1e-3) / 1e9
     alg = algorithmic_bytes(R, C, nnz, kz, b)
-    dominant = max(("sddmm", "spmm"), key=lambda n: per_kernel_ms[n])
+    dominant = max(names, key=lambda n: per_kernel_ms[n])
     achieved = alg[dominant] / (per_kernel_ms[dominant] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
     workload = "rmat24-deg16-block(5,2)-8x8x4-kz32"
@@ -204,7 +227,8 @@ def main():
         "data": "synthetic (seeded R-MAT stand-in for the paper's SuiteSparse graphs)",
         "config": {"workload": workload, "rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4",
                    "block": [5, 2], "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
-                   "step": "gather A, gather B, SDDMM, SpMM, scatter-reduce"},
+                   "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
+                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce")},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -73,10 +73,11 @@ enum { SPC3D_OVERWRITE = 0, SPC3D_ACCUMULATE = 1 };  /* output modes */
 enum { SPC3D_BUILD_CSC = 1u };                        /* plan flags */
 enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
 
-/* Kernel variant for sddmm / spmm: -1 lets the library choose; otherwise
- * (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64, 0..4) << 4.
- * Every valid variant computes the same result within the stated tolerance. */
-#define SPC3D_VARIANT(lg_lanes, lg_items) ((lg_lanes) | ((lg_items) << 4))
+/* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose;
+ * otherwise (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64,
+ * 0..4) << 4 | (prefetch the next batch of rows in SpMM, 0..1) << 8.  Every
+ * valid variant computes the same result within the stated tolerance. */
+#define SPC3D_VARIANT(lg_lanes, lg_items, pipe) ((lg_lanes) | ((lg_items) << 4) | ((pipe) << 8))
 
 typedef struct spc3d_plan_s* spc3d_plan;
 
@@ -171,6 +172,19 @@ spc3d_status spc3d_spmm_buffer_size(spc3d_plan plan, int transpose, int32_t kz, 
 spc3d_status spc3d_spmm(spc3d_plan plan, int transpose, const float* d_vals, const void* d_X,
                         spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant,
                         void* d_buf, size_t buf_bytes, hipStream_t stream);
+
+/* SDDMM and SpMM of the same block in one pass over its slots (the pattern
+ * the paper's comparison runs: SDDMM followed by SpMM with the same sparse
+ * matrix and the same B rows; Section "Experimental Evaluation").  Computes
+ *   d_out[p] (=|+=) s_p * <A[i(p)], B[j(p)]>          (as spc3d_sddmm)
+ *   d_Y[i]   (=|+=) sum_{p in row i} s_p * B[j(p)]    (as spc3d_spmm, transpose 0)
+ * reading each entry's packed B row once for both.  Arguments as for
+ * spc3d_sddmm and spc3d_spmm; d_buf holds spc3d_spmm_buffer_size(plan, 0, kz,
+ * variant) bytes.  Neither output may alias an input. */
+spc3d_status spc3d_sddmm_spmm(spc3d_plan plan, const float* d_vals, const void* d_A,
+                              const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
+                              float* d_Y, int mode, int variant, void* d_buf, size_t buf_bytes,
+                              hipStream_t stream);
 
 /* PostComm, local side: SpC-BB unpacking with reduction at the owner (paper:
  * "Building SpMM with SpComm3D", partial A rows sent to their owners):

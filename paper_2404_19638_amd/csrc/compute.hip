@@ -45,6 +45,52 @@ __device__ inline bool is_head(const uint64_t* __restrict__ head, int64_t s) {
   return (head[s >> 6] >> (s & 63)) & 1ull;
 }
 
+// Sum of v over the L lanes of a group (a butterfly: DPP within 16-lane
+// rows, cross-lane permutes beyond).  Every lane of the group gets the sum.
+template <int LPN>
+__device__ inline float group_sum(float v) {
+  if constexpr (LPN >= 2)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  if constexpr (LPN >= 4)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  if constexpr (LPN >= 8)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  if constexpr (LPN >= 16)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  if constexpr (LPN >= 32) v += __shfl_xor(v, 16);
+  if constexpr (LPN >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Loads this lane's NCH vectors of a kz-wide row.  Vectors past the row end
+// (lanes left over when kz/VEC is not a multiple of L) re-read the last
+// vector so that no load is predicated; callers ignore them.
+template <typename T, int VEC, int LPN, int NCH>
+__device__ inline void load_row(const T* __restrict__ row, int q, int nvec, float (&x)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    int vi = q + ch * LPN;
+    vi = vi < nvec ? vi : nvec - 1;
+    VecLoad<T, VEC>::load(row + vi * VEC, x[ch]);
+  }
+}
+
+template <int VEC, int LPN, int NCH>
+__device__ inline float lane_dot(const float (&a)[NCH][VEC], const float (&b)[NCH][VEC], int q,
+                                 int nvec) {
+  float acc = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const bool on = q + ch * LPN < nvec;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      const float f = fmaf(a[ch][t], b[ch][t], acc);
+      acc = on ? f : acc;
+    }
+  }
+  return acc;
+}
+
 // ------------------------------------------------------------------ SDDMM
 
 template <typename T, int VEC, int LPN, int NCH>
@@ -55,6 +101,10 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int6
                                                const float* __restrict__ vals,
                                                const T* __restrict__ A, const T* __restrict__ B,
                                                int kz, float* __restrict__ out, int accumulate) {
+  // JB nonzeros per group have their rows in flight together (2*JB*NCH*VEC
+  // registers of loads).
+  constexpr int JB0 = 64 / (2 * NCH * VEC);
+  constexpr int JB = JB0 < 1 ? 1 : (JB0 > LPN ? LPN : JB0);
   const int lane = threadIdx.x & 63;
   const int g = lane / LPN, q = lane % LPN;
   const int64_t item = xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
@@ -67,28 +117,25 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int6
     const bool valid = s < e;
     const int col = valid ? colidx[s] : 0;
     const float v = vals ? (valid ? vals[s] : 0.f) : 1.f;
+    // lanes past the end repeat the last valid row (no head bits there)
     const int row = tile_row[win >> 6] + __popcll(head[win >> 6] & lanemask_le(lane) & ~1ull);
     float res = 0.f;
 #pragma unroll
-    for (int j = 0; j < LPN; ++j) {
-      const int src = g * LPN + j;
-      const int c = __shfl(col, src);
-      const int r = __shfl(row, src);   // lanes past the end repeat a valid row
-      float acc = 0.f;
+    for (int j0 = 0; j0 < LPN; j0 += JB) {
+      float a[JB][NCH][VEC], bb[JB][NCH][VEC];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
-        const int vi = q + ch * LPN;
-        if (vi < nvec) {
-          float a[VEC], bb[VEC];
-          VecLoad<T, VEC>::load(A + (int64_t)r * kz + vi * VEC, a);
-          VecLoad<T, VEC>::load(B + (int64_t)c * kz + vi * VEC, bb);
-#pragma unroll
-          for (int t = 0; t < VEC; ++t) acc = fmaf(a[t], bb[t], acc);
-        }
+      for (int jj = 0; jj < JB; ++jj) {
+        const int src = g * LPN + j0 + jj;
+        const int c = __shfl(col, src);
+        const int r = __shfl(row, src);
+        load_row<T, VEC, LPN, NCH>(A + (int64_t)r * kz, q, nvec, a[jj]);
+        load_row<T, VEC, LPN, NCH>(B + (int64_t)c * kz, q, nvec, bb[jj]);
       }
 #pragma unroll
-      for (int o = LPN / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-      if (q == j) res = acc;
+      for (int jj = 0; jj < JB; ++jj) {
+        const float d = group_sum<LPN>(lane_dot<VEC, LPN, NCH>(a[jj], bb[jj], q, nvec));
+        if (q == j0 + jj) res = d;
+      }
     }
     if (valid) {
       const float o = v * res;
@@ -159,13 +206,51 @@ __device__ inline void zero(float (&acc)[NCH][VEC]) {
     for (int t = 0; t < VEC; ++t) acc[ch][t] = 0.f;
 }
 
-// LDS bytes one wavefront of k_spmm uses.
-inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec) {
+// LDS bytes one wavefront of k_spmm uses (fused: plus the SDDMM outputs).
+inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec, bool fused) {
   const int G = 64 / lpn;
-  return (size_t)wslots * 8 + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4;
+  return (size_t)wslots * (fused ? 12 : 8) + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4;
 }
 
-template <typename T, int VEC, int LPN, int NCH>
+// One batch of UB consecutive slots of a group: their columns, values, head
+// bits and the rows they gather (and, fused, the A rows of their own rows).
+template <typename T, int VEC, int LPN, int NCH, int UB, bool FUSED>
+struct Batch {
+  float x[UB][NCH][VEC];
+  float a[FUSED ? UB : 1][NCH][VEC];
+  float v[UB];
+  unsigned hbits;
+};
+
+template <typename T, int VEC, int LPN, int NCH, int UB, bool FUSED>
+__device__ inline void load_batch(Batch<T, VEC, LPN, NCH, UB, FUSED>& bt, int64_t s0, int64_t b,
+                                  int64_t ge, const int* s_col, const float* s_val,
+                                  const uint64_t* __restrict__ head,
+                                  const int32_t* __restrict__ tile_row, const T* __restrict__ X,
+                                  const T* __restrict__ A, int kz, int q, int nvec, int rvalid) {
+  const bool any = s0 < ge;
+  const int64_t sw = any ? s0 : b;   // a valid slot for the head word
+  const uint64_t hw = head[sw >> 6];
+  bt.hbits = (unsigned)(hw >> (sw & 63)) & ((1u << UB) - 1u);
+  int rbase = 0;
+  if constexpr (FUSED) rbase = tile_row[sw >> 6] + __popcll(hw & lanemask_le((int)(sw & 63)) & ~1ull);
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const bool ok = s0 + u < ge;
+    const int li = ok ? (int)(s0 - b) + u : 0;
+    const int c = s_col[li];
+    bt.v[u] = ok ? s_val[li] : 0.f;
+    load_row<T, VEC, LPN, NCH>(X + (int64_t)c * kz, q, nvec, bt.x[u]);
+    if constexpr (FUSED) {
+      const int r = ok ? rbase + __popc(bt.hbits & ((2u << u) - 1u) & ~1u) : rvalid;
+      load_row<T, VEC, LPN, NCH>(A + (int64_t)r * kz, q, nvec, bt.a[u]);
+    }
+  }
+}
+
+// SpMM (and, with FUSED, SDDMM on the same pass: every slot's packed B row is
+// read once and used both for the dot with its A row and for the row sum).
+template <typename T, int VEC, int LPN, int NCH, bool FUSED, bool PIPE>
 __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64_t nblocks,
                                               int wslots, const int32_t* __restrict__ idx,
                                               const uint64_t* __restrict__ head,
@@ -174,18 +259,24 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
                                               const int32_t* __restrict__ vidx,
                                               const T* __restrict__ X, int kz,
                                               float* __restrict__ Y, int accumulate,
-                                              float* __restrict__ carry) {
+                                              float* __restrict__ carry, const T* __restrict__ A,
+                                              float* __restrict__ out) {
   constexpr int G = 64 / LPN;
-  constexpr int UB = 8 / NCH;              // slots whose rows are loaded together
-  constexpr int KW = LPN * NCH * VEC;      // padded row width of one group
+  constexpr int UB0 = (FUSED ? 16 : 32) / (NCH * VEC);
+  constexpr int UB = UB0 < 1 ? 1 : (UB0 > 8 ? 8 : UB0);   // divides 8
+  constexpr int KW = LPN * NCH * VEC;
+  using BT = Batch<T, VEC, LPN, NCH, UB, FUSED>;
   extern __shared__ __align__(16) char smem[];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / LPN, q = lane % LPN;
-  char* wbase = smem + (size_t)wv * ((size_t)wslots * 8 + (size_t)G * KW * 4 + (size_t)G * 4);
+  const size_t wave_bytes = (size_t)wslots * (FUSED ? 12 : 8) + (size_t)G * KW * 4 + (size_t)G * 4;
+  char* wbase = smem + (size_t)wv * wave_bytes;
   int* s_col = reinterpret_cast<int*>(wbase);
   float* s_val = reinterpret_cast<float*>(wbase + (size_t)wslots * 4);
-  float* s_lead = reinterpret_cast<float*>(wbase + (size_t)wslots * 8);
-  int* s_kind = reinterpret_cast<int*>(wbase + (size_t)wslots * 8 + (size_t)G * KW * 4);
+  float* s_out = reinterpret_cast<float*>(wbase + (size_t)wslots * 8);   // FUSED only
+  float* s_lead = reinterpret_cast<float*>(wbase + (size_t)wslots * (FUSED ? 12 : 8));
+  int* s_kind = reinterpret_cast<int*>(wbase + (size_t)wslots * (FUSED ? 12 : 8) +
+                                       (size_t)G * KW * 4);
 
   const int64_t item = xcd_block(nblocks) * 4 + wv;
   const bool active = item < nitems;
@@ -212,31 +303,29 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
   if (active && gs < ge) {
     cur = row_of(head, tile_row, gs);
     started = is_head(head, gs);
+    const int rvalid = cur;
+    BT cb, nb;
+    if (PIPE)
+      load_batch<T, VEC, LPN, NCH, UB, FUSED>(cb, gs, b, ge, s_col, s_val, head, tile_row, X, A,
+                                              kz, q, nvec, rvalid);
     for (int64_t s0 = gs; s0 < ge; s0 += UB) {
-      const unsigned hbits = (unsigned)(head[s0 >> 6] >> (s0 & 63)) & ((1u << UB) - 1u);
-      float x[UB][NCH][VEC];
-      float vv[UB];
+      if (PIPE)   // next batch in flight while this one is reduced
+        load_batch<T, VEC, LPN, NCH, UB, FUSED>(nb, s0 + UB, b, ge, s_col, s_val, head, tile_row,
+                                                X, A, kz, q, nvec, rvalid);
+      else
+        load_batch<T, VEC, LPN, NCH, UB, FUSED>(cb, s0, b, ge, s_col, s_val, head, tile_row, X,
+                                                A, kz, q, nvec, rvalid);
+      if constexpr (FUSED) {
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const bool ok = s0 + u < ge;
-        const int li = ok ? (int)(s0 - b) + u : 0;
-        const int c = s_col[li];
-        vv[u] = ok ? s_val[li] : 0.f;
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          const int vi = q + ch * LPN;
-          if (vi < nvec) {
-            VecLoad<T, VEC>::load(X + (int64_t)c * kz + vi * VEC, x[u][ch]);
-          } else {
-#pragma unroll
-            for (int t = 0; t < VEC; ++t) x[u][ch][t] = 0.f;
-          }
+        for (int u = 0; u < UB; ++u) {
+          const float d = group_sum<LPN>(lane_dot<VEC, LPN, NCH>(cb.a[u], cb.x[u], q, nvec));
+          if (q == 0 && s0 + u < ge) s_out[s0 - b + u] = cb.v[u] * d;
         }
       }
 #pragma unroll
       for (int u = 0; u < UB; ++u) {
         if (s0 + u < ge) {
-          if (s0 + u > gs && ((hbits >> u) & 1u)) {
+          if (s0 + u > gs && ((cb.hbits >> u) & 1u)) {
             if (started) {
               store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
             } else {
@@ -250,9 +339,10 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
 #pragma unroll
           for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-            for (int t = 0; t < VEC; ++t) acc[ch][t] = fmaf(vv[u], x[u][ch][t], acc[ch][t]);
+            for (int t = 0; t < VEC; ++t) acc[ch][t] = fmaf(cb.v[u], cb.x[u][ch][t], acc[ch][t]);
         }
       }
+      if (PIPE) cb = nb;
     }
     const bool ends = (ge >= nnz) || is_head(head, ge);
     if (started) {
@@ -269,6 +359,10 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
   __syncthreads();
   if (!active) return;
 
+  if constexpr (FUSED) {
+    for (int i = lane; i < (int)(e - b); i += 64)
+      out[b + i] = accumulate ? out[b + i] + s_out[i] : s_out[i];
+  }
   if (tail) {
     bool done = false;
     for (int g2 = g + 1; g2 < G; ++g2) {
@@ -364,6 +458,7 @@ struct Shape {
   int lanes;  // L
   int nch;    // vectors per lane
   int items;  // W
+  int pipe;   // SpMM: prefetch the next batch while reducing the current one
 };
 
 int pow2ceil(int n) {
@@ -385,12 +480,14 @@ spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, bool sp
     if (sh->lanes < 2) sh->lanes = 2;
     while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
     sh->items = 256;
+    sh->pipe = 0;
   } else {
     const int lg = variant & 15, lw = (variant >> 4) & 15;
-    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 8))
+    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 9))
       return fail(SPC3D_ERR_INVALID_ARG, "bad variant %d", variant);
     sh->lanes = 1 << lg;
     sh->items = 64 << lw;
+    sh->pipe = (variant >> 8) & 1;
   }
   sh->nch = (nvec + sh->lanes - 1) / sh->lanes;
   if (sh->nch == 3) sh->nch = 4;
@@ -432,17 +529,66 @@ void launch_sddmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, 
                          accumulate)));
 }
 
-template <typename T, int VEC>
+template <typename T, int VEC, bool FUSED>
 void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
                  const Orient& o, const float* vals, const void* X, int kz, float* Y,
-                 int accumulate, float* carry, size_t lds) {
+                 int accumulate, float* carry, size_t lds, const void* A, float* out) {
   SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
-      hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_>), dim3((unsigned)nblocks), dim3(256), lds,
-                         st, nnz, nitems, nblocks, sh.items, o.idx, o.head, o.tile_row, vals,
-                         o.vidx, static_cast<const T*>(X), kz, Y, accumulate, carry);
+      if (sh.pipe)
+        hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, true>), dim3((unsigned)nblocks),
+                           dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
+                           o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
+                           carry, static_cast<const T*>(A), out);
+      else
+        hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, false>), dim3((unsigned)nblocks),
+                           dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
+                           o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
+                           carry, static_cast<const T*>(A), out);
       hipLaunchKernelGGL((k_spmm_fixup<VEC, LPN_, NCH_>),
                          dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, st, nnz, nitems,
                          sh.items, o.ptr, o.head, o.tile_row, kz, Y, accumulate, carry)));
+}
+
+// Shared body of spc3d_spmm and spc3d_sddmm_spmm.
+spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d_X,
+                      spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant, void* d_buf,
+                      size_t buf_bytes, hipStream_t stream, const void* d_A, float* d_out) {
+  const bool fused = d_A != nullptr;
+  Shape sh;
+  const bool al = aligned16(d_X) && aligned16(d_Y) && (!fused || aligned16(d_A));
+  spc3d_status st = pick_shape(kz, x_t, al, variant, true, &sh);
+  if (st != SPC3D_OK) return st;
+  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
+  if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
+    return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes,
+                (size_t)nitems * 2 * (size_t)kz * 4);
+  const size_t lds = 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec, fused);
+  if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
+  st = use_device(p);
+  if (st != SPC3D_OK) return st;
+  const int64_t nblocks = (nitems + 3) / 4;
+  const Orient o = transpose ? p->csc() : p->csr();
+  const int acc = mode == SPC3D_ACCUMULATE;
+  float* carry = static_cast<float*>(d_buf);
+#define SPC3D_RUN(T, V)                                                                        \
+  do {                                                                                         \
+    if (fused)                                                                                 \
+      launch_spmm<T, V, true>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y,    \
+                              acc, carry, lds, d_A, d_out);                                    \
+    else                                                                                       \
+      launch_spmm<T, V, false>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y,   \
+                               acc, carry, lds, nullptr, nullptr);                             \
+  } while (0)
+  if (x_t == SPC3D_F32) {
+    if (sh.vec == 4) SPC3D_RUN(float, 4);
+    else SPC3D_RUN(float, 1);
+  } else {
+    if (sh.vec == 8) SPC3D_RUN(bf16_t, 8);
+    else SPC3D_RUN(bf16_t, 1);
+  }
+#undef SPC3D_RUN
+  SPC3D_LAUNCHED(fused ? "sddmm_spmm" : "spmm");
+  return SPC3D_OK;
 }
 
 }  // namespace
@@ -528,38 +674,26 @@ spc3d_status spc3d_spmm(spc3d_plan h, int transpose, const float* d_vals, const 
   if (!d_X || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
-  Shape sh;
-  st = pick_shape(kz, x_t, aligned16(d_X) && aligned16(d_Y), variant, true, &sh);
+  return run_spmm(p, transpose, d_vals, d_X, x_t, kz, d_Y, mode, variant, d_buf, buf_bytes,
+                  stream, nullptr, nullptr);
+}
+
+spc3d_status spc3d_sddmm_spmm(spc3d_plan h, const float* d_vals, const void* d_A, const void* d_B,
+                              spc3d_dtype ab_t, int32_t kz, float* d_out, float* d_Y, int mode,
+                              int variant, void* d_buf, size_t buf_bytes, hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
   if (st != SPC3D_OK) return st;
-  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
-  if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
-    return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes,
-                (size_t)nitems * 2 * (size_t)kz * 4);
-  const size_t lds = 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec);
-  if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
-  st = use_device(p);
-  if (st != SPC3D_OK) return st;
-  const int64_t nblocks = (nitems + 3) / 4;
-  const Orient o = transpose ? p->csc() : p->csr();
-  const int acc = mode == SPC3D_ACCUMULATE;
-  float* carry = static_cast<float*>(d_buf);
-  if (x_t == SPC3D_F32) {
-    if (sh.vec == 4)
-      launch_spmm<float, 4>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
-                            carry, lds);
-    else
-      launch_spmm<float, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
-                            carry, lds);
-  } else {
-    if (sh.vec == 8)
-      launch_spmm<bf16_t, 8>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
-                             carry, lds);
-    else
-      launch_spmm<bf16_t, 1>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y, acc,
-                             carry, lds);
-  }
-  SPC3D_LAUNCHED("spmm");
-  return SPC3D_OK;
+  if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
+  if (mode != SPC3D_OVERWRITE && mode != SPC3D_ACCUMULATE)
+    return fail(SPC3D_ERR_INVALID_ARG, "bad mode");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_A || !d_B || !d_out || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
+    return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
+  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, d_Y, mode, variant, d_buf, buf_bytes, stream, d_A,
+                  d_out);
 }
 
 }  // extern "C"

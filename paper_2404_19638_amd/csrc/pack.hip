@@ -6,15 +6,75 @@
 // rows (or columns) in local-id order, and unpacking reduces (+=) into the
 // owner's rows as the SpMM PostComm does ("Building SpMM with SpComm3D").
 //
-// Both kernels stream: every thread moves one 16-byte chunk (4 FP32 or 8
-// bfloat16 values), so a packed FP32 row with kz = 32 is one 128-byte line.
+// Both kernels stream in 16-byte chunks (4 FP32 or 8 bfloat16 values), so a
+// packed FP32 row with kz = 32 is one 128-byte line.
+#include <type_traits>
+
 #include "internal.h"
 #include "vec.h"
 
 namespace spc3d {
 
-// packed[l*kz + k] = conv(src[(gmap[l]-lo)*ld + k0 + k]); VO output elements
-// per thread.
+// Each thread moves kUnroll chunks of VO output elements, all loads of a
+// thread issued before its stores (1 measured best: more threads in flight).
+constexpr int kUnroll = 1;
+
+template <typename Tin, typename Tout, int VO>
+struct Chunk;
+
+template <>
+struct Chunk<float, float, 4> {
+  float4 v;
+  __device__ void load(const float* s) { v = *reinterpret_cast<const float4*>(s); }
+  __device__ void store(float* d) const { *reinterpret_cast<float4*>(d) = v; }
+};
+
+template <>
+struct Chunk<float, bf16_t, 8> {
+  float4 a, b;
+  __device__ void load(const float* s) {
+    a = reinterpret_cast<const float4*>(s)[0];
+    b = reinterpret_cast<const float4*>(s)[1];
+  }
+  __device__ void store(bf16_t* d) const {
+    uint4 o;
+    o.x = (uint32_t)f32_to_bf16(a.x) | ((uint32_t)f32_to_bf16(a.y) << 16);
+    o.y = (uint32_t)f32_to_bf16(a.z) | ((uint32_t)f32_to_bf16(a.w) << 16);
+    o.z = (uint32_t)f32_to_bf16(b.x) | ((uint32_t)f32_to_bf16(b.y) << 16);
+    o.w = (uint32_t)f32_to_bf16(b.z) | ((uint32_t)f32_to_bf16(b.w) << 16);
+    *reinterpret_cast<uint4*>(d) = o;
+  }
+};
+
+template <>
+struct Chunk<bf16_t, bf16_t, 8> {
+  uint4 v;
+  __device__ void load(const bf16_t* s) { v = *reinterpret_cast<const uint4*>(s); }
+  __device__ void store(bf16_t* d) const { *reinterpret_cast<uint4*>(d) = v; }
+};
+
+template <>
+struct Chunk<float, float, 1> {
+  float v;
+  __device__ void load(const float* s) { v = *s; }
+  __device__ void store(float* d) const { *d = v; }
+};
+
+template <>
+struct Chunk<float, bf16_t, 1> {
+  float v;
+  __device__ void load(const float* s) { v = *s; }
+  __device__ void store(bf16_t* d) const { *d = f32_to_bf16(v); }
+};
+
+template <>
+struct Chunk<bf16_t, bf16_t, 1> {
+  bf16_t v;
+  __device__ void load(const bf16_t* s) { v = *s; }
+  __device__ void store(bf16_t* d) const { *d = v; }
+};
+
+// packed[l*kz + k] = conv(src[(gmap[l]-lo)*ld + k0 + k]), VO elements per chunk.
 template <typename Tin, typename Tout, int VO>
 __global__ __launch_bounds__(256) void k_gather(int64_t n, const int64_t* __restrict__ gmap,
                                                 int64_t lo, const Tin* __restrict__ src,
@@ -22,60 +82,75 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, const int64_t* __rest
                                                 Tout* __restrict__ dst) {
   const int chunks = kz / VO;
   const int64_t total = n * chunks;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t l = i / chunks;
-    const int c = (int)(i - l * chunks);
-    const Tin* s = src + (gmap[l] - lo) * ld + k0 + (int64_t)c * VO;
-    Tout* d = dst + l * kz + (int64_t)c * VO;
-    if constexpr (VO == 4 && sizeof(Tin) == 4 && sizeof(Tout) == 4) {
-      *reinterpret_cast<float4*>(d) = *reinterpret_cast<const float4*>(s);
-    } else if constexpr (VO == 8 && sizeof(Tin) == 4 && sizeof(Tout) == 2) {
-      const float4 a = reinterpret_cast<const float4*>(s)[0];
-      const float4 b = reinterpret_cast<const float4*>(s)[1];
-      uint4 o;
-      o.x = (uint32_t)f32_to_bf16(a.x) | ((uint32_t)f32_to_bf16(a.y) << 16);
-      o.y = (uint32_t)f32_to_bf16(a.z) | ((uint32_t)f32_to_bf16(a.w) << 16);
-      o.z = (uint32_t)f32_to_bf16(b.x) | ((uint32_t)f32_to_bf16(b.y) << 16);
-      o.w = (uint32_t)f32_to_bf16(b.z) | ((uint32_t)f32_to_bf16(b.w) << 16);
-      *reinterpret_cast<uint4*>(d) = o;
-    } else if constexpr (VO == 8 && sizeof(Tin) == 2 && sizeof(Tout) == 2) {
-      *reinterpret_cast<uint4*>(d) = *reinterpret_cast<const uint4*>(s);
-    } else if constexpr (sizeof(Tin) == 4 && sizeof(Tout) == 2) {
-      d[0] = f32_to_bf16(reinterpret_cast<const float*>(s)[0]);
-    } else {
-      d[0] = s[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kUnroll + threadIdx.x; base < total;
+       base += stride) {
+    Chunk<Tin, Tout, VO> c[kUnroll];
+    int64_t at[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      at[u] = i;
+      if (i < total) {
+        const int64_t l = i / chunks;
+        const int ci = (int)(i - l * chunks);
+        c[u].load(src + (gmap[l] - lo) * ld + k0 + (int64_t)ci * VO);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (at[u] < total) {
+        const int64_t l = at[u] / chunks;
+        const int ci = (int)(at[u] - l * chunks);
+        c[u].store(dst + l * kz + (int64_t)ci * VO);
+      }
     }
   }
 }
 
-// dst[(gmap[l]-lo)*ld + k0 + k] += packed[l*kz + k]; VO elements per thread.
+// dst[(gmap[l]-lo)*ld + k0 + k] += packed[l*kz + k]; VO elements per chunk.
 template <int VO>
 __global__ __launch_bounds__(256) void k_scatter_add(int64_t n, const int64_t* __restrict__ gmap,
                                                      int64_t lo, const float* __restrict__ packed,
                                                      int kz, float* __restrict__ dst, int64_t ld,
                                                      int k0) {
+  using V = typename std::conditional<VO == 4, float4, float>::type;
   const int chunks = kz / VO;
   const int64_t total = n * chunks;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t l = i / chunks;
-    const int c = (int)(i - l * chunks);
-    float* d = dst + (gmap[l] - lo) * ld + k0 + (int64_t)c * VO;
-    const float* s = packed + l * kz + (int64_t)c * VO;
-    if constexpr (VO == 4) {
-      float4 a = *reinterpret_cast<const float4*>(d);
-      const float4 b = *reinterpret_cast<const float4*>(s);
-      a.x = a.x + b.x; a.y = a.y + b.y; a.z = a.z + b.z; a.w = a.w + b.w;
-      *reinterpret_cast<float4*>(d) = a;
-    } else {
-      d[0] = d[0] + s[0];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * kUnroll + threadIdx.x; base < total;
+       base += stride) {
+    V a[kUnroll], b[kUnroll];
+    float* d[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = base + (int64_t)u * blockDim.x;
+      d[u] = nullptr;
+      if (i < total) {
+        const int64_t l = i / chunks;
+        const int ci = (int)(i - l * chunks);
+        d[u] = dst + (gmap[l] - lo) * ld + k0 + (int64_t)ci * VO;
+        a[u] = *reinterpret_cast<const V*>(d[u]);
+        b[u] = *reinterpret_cast<const V*>(packed + l * kz + (int64_t)ci * VO);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (d[u]) {
+        V r = a[u];
+        if constexpr (VO == 4) {
+          r.x = a[u].x + b[u].x; r.y = a[u].y + b[u].y; r.z = a[u].z + b[u].z; r.w = a[u].w + b[u].w;
+        } else {
+          r = a[u] + b[u];
+        }
+        *reinterpret_cast<V*>(d[u]) = r;
+      }
     }
   }
 }
 
 static unsigned grid_chunks(int64_t total) {
-  int64_t b = (total + 255) / 256;
+  int64_t b = (total + 256 * kUnroll - 1) / (256 * kUnroll);
   if (b < 1) b = 1;
   if (b > (1 << 20)) b = 1 << 20;
   return (unsigned)b;

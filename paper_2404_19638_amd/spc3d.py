@@ -24,9 +24,10 @@ BUILD_CSC = 1
 CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
 
 
-def variant(lg_lanes: int, lg_items: int) -> int:
-    """SPC3D_VARIANT: 2^lg_lanes lanes per nonzero, 64 * 2^lg_items slots per item."""
-    return lg_lanes | (lg_items << 4)
+def variant(lg_lanes: int, lg_items: int, pipe: int = 0) -> int:
+    """SPC3D_VARIANT: 2^lg_lanes lanes per nonzero, 64 * 2^lg_items slots per work item;
+    pipe=1 prefetches the next batch of rows in SpMM."""
+    return lg_lanes | (lg_items << 4) | (pipe << 8)
 
 
 class Spc3dError(RuntimeError):
@@ -59,6 +60,8 @@ def lib():
         "spc3d_spmm_buffer_size": [vp, ctypes.c_int, i32, ctypes.c_int, P(sz)],
         "spc3d_spmm": [vp, ctypes.c_int, vp, vp, ctypes.c_int, i32, vp, ctypes.c_int, ctypes.c_int,
                        vp, sz, vp],
+        "spc3d_sddmm_spmm": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int,
+                             ctypes.c_int, vp, sz, vp],
         "spc3d_scatter_reduce": [vp, ctypes.c_int, vp, i32, vp, i64, i32, vp],
         "spc3d_permute_values": [vp, ctypes.c_int, vp, vp, vp],
         "spc3d_row_softmax_buffer_size": [vp, P(sz)],
@@ -256,6 +259,34 @@ def spmm(plan: Plan, vals, X: torch.Tensor, transpose: int = 0, kz: int | None =
                             _ptr(out), mode, variant, _ptr(buf), buf.numel(), _stream(stream)),
            "spc3d_spmm")
     return out
+
+
+def sddmm_spmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | None = None,
+               out: torch.Tensor | None = None, Y: torch.Tensor | None = None,
+               mode: int = OVERWRITE, variant: int = -1, buf: torch.Tensor | None = None,
+               stream=None):
+    """SDDMM (slot-order out) and SpMM (Y = S B) in one pass; returns (out, Y)."""
+    kz = A.shape[1] if kz is None else kz
+    _need(A.dtype == B.dtype, "A and B must share a dtype")
+    _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
+    _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
+          "vals must hold nnz FP32 values")
+    if out is None:
+        out = torch.empty(plan.nnz, dtype=torch.float32, device=A.device)
+    if Y is None:
+        Y = torch.empty((plan.R, kz), dtype=torch.float32, device=A.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
+          "out must hold nnz FP32 values")
+    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz,
+          "Y too small")
+    need = spmm_buffer_size(plan, 0, kz, variant)
+    if buf is None:
+        buf = plan.buffer(("spmm", 0), need)
+    _check(lib().spc3d_sddmm_spmm(plan.handle, _ptr(vals), _ptr(A), _ptr(B), _dtype_code(A), kz,
+                                  _ptr(out), _ptr(Y), mode, variant, _ptr(buf), buf.numel(),
+                                  _stream(stream)), "spc3d_sddmm_spmm")
+    return out, Y
 
 
 def scatter_reduce(plan: Plan, axis: int, packed: torch.Tensor, dst: torch.Tensor, k0: int,

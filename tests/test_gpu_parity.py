@@ -174,7 +174,7 @@ def _local_inputs(p, ref, k0, kz, dtype=np.float32):
     return Aloc, Bloc
 
 
-VARIANTS = [-1, (1, 2), (2, 1), (3, 0), (3, 2), (3, 4), (4, 2), (5, 3), (6, 4)]
+VARIANTS = [-1, (1, 2), (2, 1), (3, 0), (3, 2), (3, 4), (4, 2), (5, 3), (6, 4), (3, 3, 1), (1, 2, 1)]
 
 
 def _variant(spc, v):
@@ -218,6 +218,9 @@ def test_sddmm_spmm_parity(name, kz):
         assert_within_mag(_np(Y), o_sp, m_sp, what=f"spmm v={v}")
         YT = spc.spmm(plan, vals_slot, A, 1, kz, variant=vv)
         assert_within_mag(_np(YT), o_spt, m_spt, what=f"spmm^T v={v}")
+        fo, fy = spc.sddmm_spmm(plan, vals_slot, A, B, kz, variant=vv)
+        assert_within_mag(_np(fo), o_sd, m_sd, what=f"fused sddmm v={v}")
+        assert_within_mag(_np(fy), o_sp, m_sp, what=f"fused spmm v={v}")
 
 
 def test_pattern_only_and_accumulate_modes():
