@@ -75,9 +75,9 @@ enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
 
 /* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose;
  * otherwise (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64,
- * 0..4) << 4 | (prefetch the next batch of rows in SpMM, 0..1) << 8.  Every
- * valid variant computes the same result within the stated tolerance. */
-#define SPC3D_VARIANT(lg_lanes, lg_items, pipe) ((lg_lanes) | ((lg_items) << 4) | ((pipe) << 8))
+ * 0..4) << 4 | (SpMM gathers 16 rows per batch instead of 8, 0..1) << 8.
+ * Every valid variant computes the same result within the stated tolerance. */
+#define SPC3D_VARIANT(lg_lanes, lg_items, wide) ((lg_lanes) | ((lg_items) << 4) | ((wide) << 8))
 
 typedef struct spc3d_plan_s* spc3d_plan;
 

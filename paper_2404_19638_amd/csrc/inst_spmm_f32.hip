@@ -1,0 +1,9 @@
+// Explicit instantiations: spmm kernels on f32 rows.
+#include "kernels.h"
+
+namespace spc3d {
+
+template void launch_spmm<float, 4, false>(SPC3D_SPMM_LAUNCH_ARGS);
+template void launch_spmm<float, 1, false>(SPC3D_SPMM_LAUNCH_ARGS);
+
+}  // namespace spc3d

@@ -1,0 +1,583 @@
+// Compute phase: SDDMM, Eq. (1), and SpMM, Eq. (2), over a localized block
+// with a K-slice of width kz (paper: Section "Building 3D SDDMM and SpMM
+// Algorithms", The Compute phase — each of the Z instances forms the inner
+// products over K/Z columns; "Building SpMM" for the row-wise SpMM).
+//
+// Work decomposition (both kernels).  The block's slots are cut into work
+// items of W consecutive slots (W a multiple of 64), one item per wavefront,
+// regardless of row boundaries, so power-law hub rows cannot serialize a
+// wavefront.  A wavefront is split into G = 64 / L groups of L lanes; a group
+// owns one nonzero at a time and each lane of it holds NCH vectors of VEC
+// elements of the kz-wide dense row (16-byte loads: 4 FP32 or 8 bfloat16).
+// Rows are recovered from a 64-bit head bitmap per 64 slots plus the row of
+// the tile's first slot (a popcount), so no per-slot row array is read.
+//
+// SDDMM: in each 64-slot window, group g computes the dots of slots
+// g*L .. g*L+L-1 one after another (lane-parallel FMAs, then an xor-butterfly
+// over the L lanes); lane i ends up holding slot i's dot and the window's 64
+// outputs are written with one coalesced store.
+//
+// SpMM: group g walks a contiguous run of S = W / G slots, accumulating
+// s_p * X[col] in registers; a row that starts and ends inside the run is
+// written directly.  Rows cut by run boundaries leave partial sums in LDS
+// (the first row of a run) or registers (the last); after one barrier the
+// group that started such a row adds the following runs' partials in run
+// order.  Rows cut by item boundaries leave per-item carries that a small
+// second kernel adds in item order (blocked, then a butterfly across groups).
+// The summation order depends only on the structure, so results are
+// deterministic, and every FP32 sum has depth O(S + G + W-items / 16), which
+// keeps the rounding error far inside 1e-5 of the magnitude sum even for rows
+// with 10^5 entries.
+#pragma once
+
+#include "internal.h"
+#include "vec.h"
+
+namespace spc3d {
+
+enum { kLeadNone = 0, kLeadEnds = 1, kLeadThrough = 2 };
+
+// Row of slot s from the head bitmap.
+__device__ inline int row_of(const uint64_t* __restrict__ head, const int32_t* __restrict__ tile_row,
+                             int64_t s) {
+  return tile_row[s >> 6] + __popcll(head[s >> 6] & lanemask_le((int)(s & 63)) & ~1ull);
+}
+
+__device__ inline bool is_head(const uint64_t* __restrict__ head, int64_t s) {
+  return (head[s >> 6] >> (s & 63)) & 1ull;
+}
+
+// Sum of v over the L lanes of a group (a butterfly: DPP within 16-lane
+// rows, cross-lane permutes beyond).  Every lane of the group gets the sum.
+template <int LPN>
+__device__ inline float group_sum(float v) {
+  if constexpr (LPN >= 2)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  if constexpr (LPN >= 4)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  if constexpr (LPN >= 8)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));
+  if constexpr (LPN >= 16)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));
+  if constexpr (LPN >= 32) v += __shfl_xor(v, 16);
+  if constexpr (LPN >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Loads this lane's NCH vectors of a kz-wide row.  Vectors past the row end
+// (lanes left over when kz/VEC is not a multiple of L) re-read the last
+// vector so that no load is predicated; callers ignore them.
+template <typename T, int VEC, int LPN, int NCH>
+__device__ inline void load_row(const T* __restrict__ row, int q, int nvec, float (&x)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    int vi = q + ch * LPN;
+    vi = vi < nvec ? vi : nvec - 1;
+    VecLoad<T, VEC>::load(row + vi * VEC, x[ch]);
+  }
+}
+
+template <int VEC, int LPN, int NCH>
+__device__ inline float lane_dot(const float (&a)[NCH][VEC], const float (&b)[NCH][VEC], int q,
+                                 int nvec) {
+  float acc = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const bool on = q + ch * LPN < nvec;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      const float f = fmaf(a[ch][t], b[ch][t], acc);
+      acc = on ? f : acc;
+    }
+  }
+  return acc;
+}
+
+// ------------------------------------------------------------------ SDDMM
+
+template <typename T, int VEC, int LPN, int NCH>
+__global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int64_t nblocks,
+                                               int wslots, const int32_t* __restrict__ colidx,
+                                               const uint64_t* __restrict__ head,
+                                               const int32_t* __restrict__ tile_row,
+                                               const float* __restrict__ vals,
+                                               const T* __restrict__ A, const T* __restrict__ B,
+                                               int kz, float* __restrict__ out, int accumulate) {
+  // JB nonzeros per group have their rows in flight together (2*JB*NCH*VEC
+  // registers of loads).
+  constexpr int JB0 = 64 / (2 * NCH * VEC);
+  constexpr int JB = JB0 < 1 ? 1 : (JB0 > LPN ? LPN : JB0);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPN, q = lane % LPN;
+  const int64_t item = xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;   // uniform per wavefront; no barriers below
+  const int nvec = kz / VEC;
+  const int64_t b = item * wslots;
+  const int64_t e = (b + wslots < nnz) ? b + wslots : nnz;
+  for (int64_t win = b; win < e; win += 64) {
+    const int64_t s = win + lane;
+    const bool valid = s < e;
+    const int col = valid ? colidx[s] : 0;
+    const float v = vals ? (valid ? vals[s] : 0.f) : 1.f;
+    // lanes past the end repeat the last valid row (no head bits there)
+    const int row = tile_row[win >> 6] + __popcll(head[win >> 6] & lanemask_le(lane) & ~1ull);
+    float res = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < LPN; j0 += JB) {
+      float a[JB][NCH][VEC], bb[JB][NCH][VEC];
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int src = g * LPN + j0 + jj;
+        const int c = __shfl(col, src);
+        const int r = __shfl(row, src);
+        load_row<T, VEC, LPN, NCH>(A + (int64_t)r * kz, q, nvec, a[jj]);
+        load_row<T, VEC, LPN, NCH>(B + (int64_t)c * kz, q, nvec, bb[jj]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const float d = group_sum<LPN>(lane_dot<VEC, LPN, NCH>(a[jj], bb[jj], q, nvec));
+        if (q == j0 + jj) res = d;
+      }
+    }
+    if (valid) {
+      const float o = v * res;
+      out[s] = accumulate ? out[s] + o : o;
+    }
+  }
+}
+
+// ------------------------------------------------------------------- SpMM
+
+template <int VEC, int NCH>
+__device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int nvec, int q,
+                                 int lpn, const float (&acc)[NCH][VEC], int accumulate) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+      float* y = Y + row * kz + vi * VEC;
+      if constexpr (VEC % 4 == 0) {
+#pragma unroll
+        for (int t = 0; t < VEC; t += 4) {
+          float4 o = make_float4(acc[ch][t], acc[ch][t + 1], acc[ch][t + 2], acc[ch][t + 3]);
+          if (accumulate) {
+            const float4 old = *reinterpret_cast<const float4*>(y + t);
+            o.x = old.x + o.x; o.y = old.y + o.y; o.z = old.z + o.z; o.w = old.w + o.w;
+          }
+          *reinterpret_cast<float4*>(y + t) = o;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) y[t] = accumulate ? y[t] + acc[ch][t] : acc[ch][t];
+      }
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void store_vec(float* __restrict__ dst, int nvec, int q, int lpn,
+                                 const float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) dst[vi * VEC + t] = acc[ch][t];
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void add_vec(const float* __restrict__ src, int nvec, int q, int lpn,
+                               float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) acc[ch][t] += src[vi * VEC + t];
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void zero(float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) acc[ch][t] = 0.f;
+}
+
+// LDS bytes one wavefront of k_spmm uses (fused: plus the SDDMM outputs).
+// Staged per-slot arrays hold one pad word per run of S = W/G slots, so the
+// G groups reading slot u of their runs hit different LDS banks.
+inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec, bool fused) {
+  const int G = 64 / lpn;
+  const size_t P = (size_t)wslots + G;
+  return P * (fused ? 12 : 8) + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4;
+}
+
+// One batch of UB consecutive slots of a group: their columns, values, head
+// bits and the rows they gather (and, fused, the A rows of their own rows).
+template <typename T, int VEC, int LPN, int NCH, int UB, bool FUSED>
+struct Batch {
+  float x[UB][NCH][VEC];
+  float a[FUSED ? UB : 1][NCH][VEC];
+  float v[UB];
+  unsigned hbits;
+  unsigned anew;   // FUSED: bit u set when a[u] holds a newly started row's A
+};
+
+template <typename T, int VEC, int LPN, int NCH, int UB, bool FUSED>
+__device__ inline void load_batch(Batch<T, VEC, LPN, NCH, UB, FUSED>& bt, int64_t s0, int64_t b,
+                                  int64_t ge, const int* s_col, const float* s_val,
+                                  const uint64_t* __restrict__ head,
+                                  const int32_t* __restrict__ tile_row, const T* __restrict__ X,
+                                  const T* __restrict__ A, int kz, int q, int nvec, int64_t gs,
+                                  int lgS) {
+  const bool any = s0 < ge;
+  const int64_t sw = any ? s0 : b;   // a valid slot for the head word
+  const uint64_t hw = head[sw >> 6];
+  bt.hbits = (unsigned)(hw >> (sw & 63)) & ((1u << UB) - 1u);
+  int rbase = 0;
+  if constexpr (FUSED) rbase = tile_row[sw >> 6] + __popcll(hw & lanemask_le((int)(sw & 63)) & ~1ull);
+#pragma unroll
+  for (int u = 0; u < UB; ++u) {
+    const bool ok = s0 + u < ge;
+    const int li0 = ok ? (int)(s0 - b) + u : 0;
+    const int li = li0 + (li0 >> lgS);
+    const int c = s_col[li];
+    bt.v[u] = ok ? s_val[li] : 0.f;
+    load_row<T, VEC, LPN, NCH>(X + (int64_t)c * kz, q, nvec, bt.x[u]);
+    if constexpr (FUSED) {
+      // one A access per row segment: at the group's first slot and where a
+      // row starts
+      const bool need = ok && (s0 + u == gs || (((bt.hbits >> u) & 1u) && s0 + u > gs));
+      if (u == 0) bt.anew = 0;
+      if (need) {
+        const int r = rbase + __popc(bt.hbits & ((2u << u) - 1u) & ~1u);
+        load_row<T, VEC, LPN, NCH>(A + (int64_t)r * kz, q, nvec, bt.a[u]);
+        bt.anew |= 1u << u;
+      }
+    }
+  }
+}
+
+// SpMM (and, with FUSED, SDDMM on the same pass: every slot's packed B row is
+// read once and used both for the dot with its A row and for the row sum).
+template <typename T, int VEC, int LPN, int NCH, bool FUSED, int UBT>
+__global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64_t nblocks,
+                                              int wslots, const int32_t* __restrict__ idx,
+                                              const uint64_t* __restrict__ head,
+                                              const int32_t* __restrict__ tile_row,
+                                              const float* __restrict__ vals,
+                                              const int32_t* __restrict__ vidx,
+                                              const T* __restrict__ X, int kz,
+                                              float* __restrict__ Y, int accumulate,
+                                              float* __restrict__ carry, const T* __restrict__ A,
+                                              float* __restrict__ out) {
+  constexpr int G = 64 / LPN;
+  constexpr int UB0 = UBT * (FUSED ? 2 : 4) / (NCH * VEC);
+  constexpr int UB = UB0 < 1 ? 1 : (UB0 > UBT ? UBT : UB0);   // divides UBT (8 or 16)
+  constexpr int KW = LPN * NCH * VEC;
+  using BT = Batch<T, VEC, LPN, NCH, UB, FUSED>;
+  extern __shared__ __align__(16) char smem[];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / LPN, q = lane % LPN;
+  const size_t P = (size_t)wslots + G;   // staged slots plus one pad word per run
+  const size_t wave_bytes = P * (FUSED ? 12 : 8) + (size_t)G * KW * 4 + (size_t)G * 4;
+  char* wbase = smem + (size_t)wv * wave_bytes;
+  int* s_col = reinterpret_cast<int*>(wbase);
+  float* s_val = reinterpret_cast<float*>(wbase + P * 4);
+  float* s_out = reinterpret_cast<float*>(wbase + P * 8);   // FUSED only
+  float* s_lead = reinterpret_cast<float*>(wbase + P * (FUSED ? 12 : 8));
+  int* s_kind = reinterpret_cast<int*>(wbase + P * (FUSED ? 12 : 8) + (size_t)G * KW * 4);
+
+  const int64_t item = xcd_block(nblocks) * 4 + wv;
+  const bool active = item < nitems;
+  const int nvec = kz / VEC;
+  const int S = wslots / G;
+  const int lgS = __builtin_ctz(S);
+  int64_t b = 0, e = 0;
+  if (active) {
+    b = item * wslots;
+    e = (b + wslots < nnz) ? b + wslots : nnz;
+    for (int i = lane; i < (int)(e - b); i += 64) {
+      const int pi = i + (i >> lgS);
+      s_col[pi] = idx[b + i];
+      s_val[pi] = vals ? vals[vidx ? vidx[b + i] : b + i] : 1.f;
+    }
+  }
+  __syncthreads();
+
+  float acc[NCH][VEC];
+  zero(acc);
+  int kind = kLeadNone;
+  bool tail = false, started = false;
+  int cur = 0;
+  const int64_t gs = b + (int64_t)g * S;
+  const int64_t ge = (gs + S < e) ? gs + S : e;
+  if (active && gs < ge) {
+    cur = row_of(head, tile_row, gs);
+    started = is_head(head, gs);
+    BT cb;
+    float acur[FUSED ? NCH : 1][VEC];
+    for (int64_t s0 = gs; s0 < ge; s0 += UB) {
+      load_batch<T, VEC, LPN, NCH, UB, FUSED>(cb, s0, b, ge, s_col, s_val, head, tile_row, X, A, kz,
+                                              q, nvec, gs, lgS);
+      if constexpr (FUSED) {
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          if ((cb.anew >> u) & 1u) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+              for (int t = 0; t < VEC; ++t) acur[ch][t] = cb.a[u][ch][t];
+          }
+          const float d = group_sum<LPN>(lane_dot<VEC, LPN, NCH>(acur, cb.x[u], q, nvec));
+          const int li = (int)(s0 - b) + u;
+          if (q == 0 && s0 + u < ge) s_out[li + (li >> lgS)] = cb.v[u] * d;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        if (s0 + u < ge) {
+          if (s0 + u > gs && ((cb.hbits >> u) & 1u)) {
+            if (started) {
+              store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+            } else {
+              store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
+              kind = kLeadEnds;
+            }
+            zero(acc);
+            ++cur;
+            started = true;
+          }
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) acc[ch][t] = fmaf(cb.v[u], cb.x[u][ch][t], acc[ch][t]);
+        }
+      }
+    }
+    const bool ends = (ge >= nnz) || is_head(head, ge);
+    if (started) {
+      if (ends)
+        store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+      else
+        tail = true;
+    } else {
+      store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
+      kind = ends ? kLeadEnds : kLeadThrough;
+    }
+  }
+  if (q == 0) s_kind[g] = kind;
+  __syncthreads();
+  if (!active) return;
+
+  if constexpr (FUSED) {
+    for (int i = lane; i < (int)(e - b); i += 64)
+      out[b + i] = accumulate ? out[b + i] + s_out[i + (i >> lgS)] : s_out[i + (i >> lgS)];
+  }
+  if (tail) {
+    bool done = false;
+    for (int g2 = g + 1; g2 < G; ++g2) {
+      const int k = s_kind[g2];
+      if (k == kLeadNone) break;
+      add_vec<VEC, NCH>(s_lead + g2 * KW, nvec, q, LPN, acc);
+      if (k == kLeadEnds) {
+        done = true;
+        break;
+      }
+    }
+    if (done)
+      store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+    else
+      store_vec<VEC, NCH>(carry + (item * 2 + 1) * kz, nvec, q, LPN, acc);
+  }
+  if (g == 0 && s_kind[0] != kLeadNone) {
+    float hc[NCH][VEC];
+    zero(hc);
+    add_vec<VEC, NCH>(s_lead, nvec, q, LPN, hc);
+    if (s_kind[0] == kLeadThrough) {
+      for (int g2 = 1; g2 < G; ++g2) {
+        const int k = s_kind[g2];
+        if (k == kLeadNone) break;
+        add_vec<VEC, NCH>(s_lead + g2 * KW, nvec, q, LPN, hc);
+        if (k == kLeadEnds) break;
+      }
+    }
+    store_vec<VEC, NCH>(carry + (item * 2) * kz, nvec, q, LPN, hc);
+  }
+}
+
+// Rows cut by item boundaries: item j whose last row starts inside it and
+// continues past its end owns the row; it adds its tail carry and the head
+// carries of the items the row runs through, in item order.
+template <int VEC, int LPN, int NCH>
+__global__ __launch_bounds__(256) void k_spmm_fixup(int64_t nnz, int64_t nitems, int wslots,
+                                                    const int32_t* __restrict__ ptr,
+                                                    const uint64_t* __restrict__ head,
+                                                    const int32_t* __restrict__ tile_row, int kz,
+                                                    float* __restrict__ Y, int accumulate,
+                                                    const float* __restrict__ carry) {
+  constexpr int G = 64 / LPN;
+  constexpr int BLK = 16;
+  const int lane = threadIdx.x & 63, g = lane / LPN, q = lane % LPN;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nitems) return;
+  const int64_t b = j * wslots, e = b + wslots;
+  if (e >= nnz || is_head(head, e)) return;
+  const int r = row_of(head, tile_row, e - 1);
+  if (ptr[r] < b) return;
+  const int64_t jl = ((int64_t)ptr[r + 1] - 1) / wslots;
+  const int nvec = kz / VEC;
+  float tot[NCH][VEC];
+  zero(tot);
+  for (int64_t j0 = j + 1 + g; j0 <= jl; j0 += (int64_t)G * BLK) {
+    float blk[NCH][VEC];
+    zero(blk);
+    for (int m = 0; m < BLK; ++m) {
+      const int64_t jj = j0 + (int64_t)m * G;
+      if (jj > jl) break;
+      add_vec<VEC, NCH>(carry + (jj * 2) * kz, nvec, q, LPN, blk);
+    }
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) tot[ch][t] += blk[ch][t];
+  }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1)
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) tot[ch][t] += __shfl_xor(tot[ch][t], m * LPN);
+  if (g == 0) {
+    float res[NCH][VEC];
+    zero(res);
+    add_vec<VEC, NCH>(carry + (j * 2 + 1) * kz, nvec, q, LPN, res);
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) res[ch][t] += tot[ch][t];
+    store_row<VEC, NCH>(Y, r, kz, nvec, q, LPN, res, accumulate);
+  }
+}
+
+// ------------------------------------------------------------ launch
+
+
+struct Shape {
+  int vec;    // elements per 16-byte load (1 = scalar path)
+  int lanes;  // L
+  int nch;    // vectors per lane
+  int items;  // W
+  int wide;   // SpMM: batches of up to 16 slots instead of 8
+};
+
+inline int pow2ceil(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// op: 0 SDDMM, 1 SpMM, 2 fused SDDMM+SpMM.  Defaults (variant -1) are the
+// best measured on MI355X for a power-law block with kz = 32: SDDMM on
+// 64-slot items, SpMM and the fused pass on 512-slot items, the fused pass
+// with half as many lanes per nonzero (its batches hold A and B rows).
+inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, int op,
+                               Shape* sh) {
+  const bool spmm = op != 0;
+  const int vfull = (t == SPC3D_F32) ? 4 : 8;
+  sh->vec = (vec_ok && kz % vfull == 0) ? vfull : 1;
+  if (sh->vec == 1 && kz > kMaxKzScalar)
+    return fail(SPC3D_ERR_UNSUPPORTED, "kz=%d needs 16-byte aligned rows with kz %% %d == 0", kz,
+                vfull);
+  const int nvec = kz / sh->vec;
+  if (variant < 0) {
+    sh->lanes = pow2ceil(nvec);
+    if (op == 2) sh->lanes /= 2;
+    if (sh->lanes > 16) sh->lanes = 16;
+    if (sh->lanes < 2) sh->lanes = 2;
+    while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
+    sh->items = spmm ? 512 : 64;
+    while (spmm && sh->items / (64 / sh->lanes) < 8) sh->items *= 2;
+    sh->wide = 0;
+  } else {
+    const int lg = variant & 15, lw = (variant >> 4) & 15;
+    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 9))
+      return fail(SPC3D_ERR_INVALID_ARG, "bad variant %d", variant);
+    sh->lanes = 1 << lg;
+    sh->items = 64 << lw;
+    sh->wide = (variant >> 8) & 1;
+  }
+  sh->nch = (nvec + sh->lanes - 1) / sh->lanes;
+  if (sh->nch == 3) sh->nch = 4;
+  if (sh->nch > 4)
+    return fail(SPC3D_ERR_UNSUPPORTED, "variant has too few lanes for kz=%d", kz);
+  if (spmm) {
+    const int G = 64 / sh->lanes;
+    if (sh->items / G < (sh->wide ? 16 : 8))
+      return fail(SPC3D_ERR_UNSUPPORTED, "SpMM variant needs >= %d slots per group",
+                  sh->wide ? 16 : 8);
+  }
+  return SPC3D_OK;
+}
+
+#define SPC3D_SWITCH_NCH(NCHV, ...)                     \
+  switch (NCHV) {                                       \
+    case 1: { constexpr int NCH_ = 1; __VA_ARGS__; break; } \
+    case 2: { constexpr int NCH_ = 2; __VA_ARGS__; break; } \
+    default: { constexpr int NCH_ = 4; __VA_ARGS__; break; } \
+  }
+
+#define SPC3D_SWITCH_LPN(LPNV, ...)                      \
+  switch (LPNV) {                                        \
+    case 2: { constexpr int LPN_ = 2; __VA_ARGS__; break; }  \
+    case 4: { constexpr int LPN_ = 4; __VA_ARGS__; break; }  \
+    case 8: { constexpr int LPN_ = 8; __VA_ARGS__; break; }  \
+    case 16: { constexpr int LPN_ = 16; __VA_ARGS__; break; } \
+    case 32: { constexpr int LPN_ = 32; __VA_ARGS__; break; } \
+    default: { constexpr int LPN_ = 64; __VA_ARGS__; break; } \
+  }
+
+template <typename T, int VEC>
+void launch_sddmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
+                  const Orient& o, const float* vals, const void* A, const void* B, int kz,
+                  float* out, int accumulate) {
+  SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
+      hipLaunchKernelGGL((k_sddmm<T, VEC, LPN_, NCH_>), dim3((unsigned)nblocks), dim3(256), 0,
+                         st, nnz, nitems, nblocks, sh.items, o.idx, o.head, o.tile_row, vals,
+                         static_cast<const T*>(A), static_cast<const T*>(B), kz, out,
+                         accumulate)));
+}
+
+template <typename T, int VEC, bool FUSED>
+void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
+                 const Orient& o, const float* vals, const void* X, int kz, float* Y,
+                 int accumulate, float* carry, size_t lds, const void* A, float* out) {
+  SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
+      if (sh.wide)
+        hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, 16>), dim3((unsigned)nblocks),
+                           dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
+                           o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
+                           carry, static_cast<const T*>(A), out);
+      else
+        hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, 8>), dim3((unsigned)nblocks),
+                           dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
+                           o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
+                           carry, static_cast<const T*>(A), out);
+      hipLaunchKernelGGL((k_spmm_fixup<VEC, LPN_, NCH_>),
+                         dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, st, nnz, nitems,
+                         sh.items, o.ptr, o.head, o.tile_row, kz, Y, accumulate, carry)));
+}
+
+#define SPC3D_SDDMM_LAUNCH_ARGS                                                                \
+  const Shape&, hipStream_t, int64_t, int64_t, int64_t, const Orient&, const float*, const void*, \
+      const void*, int, float*, int
+#define SPC3D_SPMM_LAUNCH_ARGS                                                                 \
+  const Shape&, hipStream_t, int64_t, int64_t, int64_t, const Orient&, const float*, const void*, \
+      int, float*, int, float*, size_t, const void*, float*
+
+}  // namespace spc3d

@@ -24,10 +24,10 @@ BUILD_CSC = 1
 CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
 
 
-def variant(lg_lanes: int, lg_items: int, pipe: int = 0) -> int:
+def variant(lg_lanes: int, lg_items: int, wide: int = 0) -> int:
     """SPC3D_VARIANT: 2^lg_lanes lanes per nonzero, 64 * 2^lg_items slots per work item;
-    pipe=1 prefetches the next batch of rows in SpMM."""
-    return lg_lanes | (lg_items << 4) | (pipe << 8)
+    wide=1 gathers up to 16 rows per batch in SpMM (8 otherwise)."""
+    return lg_lanes | (lg_items << 4) | (wide << 8)
 
 
 class Spc3dError(RuntimeError):

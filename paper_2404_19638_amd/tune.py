@@ -1,6 +1,6 @@
 """Exhaustive autotuner over the SDDMM / SpMM kernel variants.
 
-A variant is (log2 lanes per nonzero, log2 of work-item slots / 64, prefetch).  The
+A variant is (log2 lanes per nonzero, log2 of work-item slots / 64, wide SpMM batches).  The
 autotuner times every valid variant of an operation on a plan with HIP events
 on the current stream and returns the timings; it is the fallback of the
 learned selector and the judge of its regret.
@@ -13,8 +13,7 @@ from . import spc3d as spc
 
 LG_LANES = (1, 2, 3, 4, 5, 6)
 LG_ITEMS = (0, 1, 2, 3, 4)
-ALL_VARIANTS = [spc.variant(a, b) | (p << 8) for p in (0, 1) for a in LG_LANES
-                for b in LG_ITEMS]
+ALL_VARIANTS = [spc.variant(a, b, w) for w in (0, 1) for a in LG_LANES for b in LG_ITEMS]
 OPS = ("sddmm", "spmm", "sddmm_spmm")
 
 
