@@ -221,6 +221,13 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan plan, const float* d_alpha, const 
                                    float* d_de, void* d_buf, size_t buf_bytes,
                                    hipStream_t stream);
 
+/* Per-entry product out[p] = a[p] * b[p] for the nnz entries of a plan (slot
+ * order).  The backward of SDDMM scales the upstream gradient by the sampling
+ * values with it: d(s_p <a_i,b_j>)/d a_i = s_p b_j.  Any of the arrays may
+ * alias. */
+spc3d_status spc3d_mul_values(spc3d_plan plan, const float* d_a, const float* d_b, float* d_out,
+                              hipStream_t stream);
+
 /* ----------------------------------------------------------- diagnostics */
 
 const char* spc3d_status_string(spc3d_status status);

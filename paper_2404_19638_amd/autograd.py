@@ -1,0 +1,159 @@
+"""Hand-written backward passes of the local hot path (torch.autograd).
+
+Every forward and backward step is a call into libspc3d; PyTorch only holds
+the tensors and records the graph.  The gradients follow from the two
+definitions (Eq. (1) and Eq. (2) of the paper) by the chain rule, and each is
+itself one of the library's kernels:
+
+  SDDMM   c_p = s_p <a_i, b_j>      (i = row, j = column of slot p)
+          dA  = SpMM(S o dC, B)            dB  = SpMM^T(S o dC, A)
+          ds  = SDDMM(dC, A, B)            (sampling values dC_p)
+  SpMM    y_i = sum_p s_p b_j
+          dB  = SpMM^T(S, dY)              ds  = SDDMM(pattern, dY, B)
+  softmax alpha = rowsoftmax(e)            de  = alpha o (dalpha - rowsum(alpha o dalpha))
+  gather  packed = src[gmap]               dsrc = scatter-add(dpacked)
+  scatter dst += packed[...]               dpacked = gather(ddst)
+
+Gradients with respect to A and B of the transposed SpMM need the plan's
+column-major view (SPC3D_BUILD_CSC).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import spc3d as spc
+
+
+def _needs(ctx, i):
+    return ctx.needs_input_grad[i]
+
+
+class SDDMMFn(torch.autograd.Function):
+    """out = SDDMM(plan, vals, A, B); vals None means pattern-only (s == 1)."""
+
+    @staticmethod
+    def forward(ctx, plan, vals, A, B):
+        ctx.plan = plan
+        ctx.save_for_backward(vals if vals is not None else torch.empty(0), A, B)
+        ctx.has_vals = vals is not None
+        return spc.sddmm(plan, vals, A.contiguous(), B.contiguous())
+
+    @staticmethod
+    def backward(ctx, dout):
+        plan = ctx.plan
+        vals, A, B = ctx.saved_tensors
+        dout = dout.contiguous()
+        w = spc.mul_values(plan, dout, vals) if ctx.has_vals else dout
+        dvals = dA = dB = None
+        if ctx.has_vals and _needs(ctx, 1):
+            dvals = spc.sddmm(plan, dout, A, B)
+        if _needs(ctx, 2):
+            dA = spc.spmm(plan, w, B, transpose=0)
+        if _needs(ctx, 3):
+            dB = spc.spmm(plan, w, A, transpose=1)
+        return None, dvals, dA, dB
+
+
+class SpMMFn(torch.autograd.Function):
+    """Y = SpMM(plan, vals, X) over rows (transpose 0) or columns (transpose 1)."""
+
+    @staticmethod
+    def forward(ctx, plan, vals, X, transpose=0):
+        ctx.plan = plan
+        ctx.transpose = transpose
+        ctx.has_vals = vals is not None
+        ctx.save_for_backward(vals if vals is not None else torch.empty(0), X)
+        return spc.spmm(plan, vals, X.contiguous(), transpose=transpose)
+
+    @staticmethod
+    def backward(ctx, dY):
+        plan = ctx.plan
+        vals, X = ctx.saved_tensors
+        dY = dY.contiguous()
+        dvals = dX = None
+        if ctx.has_vals and _needs(ctx, 1):
+            # d y_i / d s_p = x_j: one dot per slot
+            if ctx.transpose == 0:
+                dvals = spc.sddmm(plan, None, dY, X)
+            else:
+                dvals = spc.sddmm(plan, None, X, dY)
+        if _needs(ctx, 2):
+            dX = spc.spmm(plan, vals if ctx.has_vals else None, dY, transpose=1 - ctx.transpose)
+        return None, dvals, dX, None
+
+
+class RowSoftmaxFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, e):
+        alpha = spc.row_softmax(plan, e.contiguous())
+        ctx.plan = plan
+        ctx.save_for_backward(alpha)
+        return alpha
+
+    @staticmethod
+    def backward(ctx, dalpha):
+        (alpha,) = ctx.saved_tensors
+        return None, spc.row_softmax_bwd(ctx.plan, alpha, dalpha.contiguous())
+
+
+class GatherFn(torch.autograd.Function):
+    """packed = rows gmap[l] - lo of src, columns [k0, k0+kz) (FP32)."""
+
+    @staticmethod
+    def forward(ctx, plan, axis, src, k0, kz):
+        ctx.plan, ctx.axis, ctx.k0, ctx.shape = plan, axis, k0, src.shape
+        return spc.gather(plan, axis, src, k0, kz)
+
+    @staticmethod
+    def backward(ctx, dpacked):
+        dsrc = torch.zeros(ctx.shape, dtype=torch.float32, device=dpacked.device)
+        spc.scatter_reduce(ctx.plan, ctx.axis, dpacked.contiguous(), dsrc, ctx.k0)
+        return None, None, dsrc, None, None
+
+
+class ScatterReduceFn(torch.autograd.Function):
+    """Returns dst + (packed rows added at gmap rows, columns k0..k0+kz)."""
+
+    @staticmethod
+    def forward(ctx, plan, axis, packed, dst, k0):
+        ctx.plan, ctx.axis, ctx.k0, ctx.kz = plan, axis, k0, packed.shape[1]
+        out = dst.clone()
+        spc.scatter_reduce(plan, axis, packed.contiguous(), out, k0)
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        dout = dout.contiguous()
+        dpacked = spc.gather(ctx.plan, ctx.axis, dout, ctx.k0, ctx.kz)
+        return None, None, dpacked, dout, None
+
+
+def sddmm(plan, vals, A, B):
+    return SDDMMFn.apply(plan, vals, A, B)
+
+
+def spmm(plan, vals, X, transpose=0):
+    return SpMMFn.apply(plan, vals, X, transpose)
+
+
+def row_softmax(plan, e):
+    return RowSoftmaxFn.apply(plan, e)
+
+
+def gather(plan, axis, src, k0, kz):
+    return GatherFn.apply(plan, axis, src, k0, kz)
+
+
+def scatter_reduce(plan, axis, packed, dst, k0):
+    return ScatterReduceFn.apply(plan, axis, packed, dst, k0)
+
+
+def gnn_attention(plan, Q, Kf, V):
+    """Masked attention over the block's pattern: SDDMM edge scores (s == 1),
+    row softmax over each row's stored entries, SpMM aggregation of V.
+
+    Q is [R, K] (local rows), Kf and V are [C, K] (local columns); returns [R, K].
+    """
+    e = sddmm(plan, None, Q, Kf)
+    alpha = row_softmax(plan, e)
+    return spmm(plan, alpha, V, 0)

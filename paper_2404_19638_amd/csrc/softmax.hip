@@ -202,6 +202,13 @@ __global__ void k_softmax_bwd_apply(int64_t nnz, const uint64_t* __restrict__ he
   }
 }
 
+__global__ void k_mul_values(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                             float* __restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x)
+    out[p] = a[p] * b[p];
+}
+
 namespace {
 
 constexpr int kRowItems = 256;   // slots per wavefront work item (4 per lane)
@@ -295,6 +302,21 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan h, const float* d_alpha, const flo
   hipLaunchKernelGGL(k_softmax_bwd_apply, dim3(blocks_for(p->nnz)), dim3(256), 0, stream,
                      p->nnz, p->head, p->tile_row, stats, d_alpha, d_dalpha, d_de);
   SPC3D_LAUNCHED("softmax bwd apply");
+  return SPC3D_OK;
+}
+
+spc3d_status spc3d_mul_values(spc3d_plan h, const float* d_a, const float* d_b, float* d_out,
+                              hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_a || !d_b || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  st = use_device(p);
+  if (st != SPC3D_OK) return st;
+  hipLaunchKernelGGL(k_mul_values, dim3(blocks_for(p->nnz)), dim3(256), 0, stream, p->nnz, d_a,
+                     d_b, d_out);
+  SPC3D_LAUNCHED("mul_values");
   return SPC3D_OK;
 }
 

@@ -67,6 +67,7 @@ def lib():
         "spc3d_row_softmax_buffer_size": [vp, P(sz)],
         "spc3d_row_softmax": [vp, vp, vp, vp, sz, vp],
         "spc3d_row_softmax_bwd": [vp, vp, vp, vp, vp, sz, vp],
+        "spc3d_mul_values": [vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -338,4 +339,13 @@ def row_softmax_bwd(plan: Plan, alpha: torch.Tensor, dalpha: torch.Tensor, out=N
     _check(lib().spc3d_row_softmax_bwd(plan.handle, _ptr(alpha), _ptr(dalpha), _ptr(out),
                                        _ptr(buf), buf.numel(), _stream(stream)),
            "spc3d_row_softmax_bwd")
+    return out
+
+
+def mul_values(plan: Plan, a: torch.Tensor, b: torch.Tensor, out=None, stream=None):
+    _need(a.numel() >= plan.nnz and b.numel() >= plan.nnz, "need nnz values")
+    _need(a.dtype == torch.float32 and b.dtype == torch.float32, "FP32 values")
+    out = torch.empty_like(a) if out is None else out
+    _check(lib().spc3d_mul_values(plan.handle, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
+           "spc3d_mul_values")
     return out

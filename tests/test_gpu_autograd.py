@@ -1,0 +1,223 @@
+"""Hand-written backward (torch.autograd.Function over libspc3d) against the
+FP64 oracle: its analytic backward, and central finite differences of its
+forward, on the 256-vertex / 2,000-entry instance with K = 8; SDDMM / SpMM /
+gather gradients with sampling values; and the attention workload (R-MAT
+2^20 vertices, average degree 32, K = 64) on sampled rows, with timings.
+
+Tolerances.  Forward and gradient entries are sums of products; each GPU
+value carries a few FP32 roundings per term (exp, division, products, sums
+of depth well under 100), so |g - g*| <= 2e-5 * M with M the sum of the
+magnitudes of the terms, computed from the oracle's own intermediates.
+"""
+import json
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_19638_amd import synth
+from helpers import assert_within_mag
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():   # pragma: no cover
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="no GPU")]
+
+DEV = "cuda:0"
+TOL = 2e-5
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _mods():
+    from paper_2404_19638_amd import autograd as ag
+    from paper_2404_19638_amd import spc3d as spc
+    return spc, ag
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _attention_magnitudes(rowptr, colidx, Q, Kf, V, alpha, dout, de):
+    """Magnitude sums M for out, dQ, dKf, dV from the oracle's intermediates."""
+    R, C = Q.shape[0], Kf.shape[0]
+    lr = np.repeat(np.arange(R), np.diff(rowptr))
+    aV = np.abs(V)
+    dal = (np.abs(dout[lr]) * aV[colidx]).sum(1)          # bounds |dalpha_p|
+    rowsum = np.bincount(lr, alpha * dal, minlength=R)
+    dem = alpha * (dal + rowsum[lr]) + np.abs(de)         # bound on |de_p| and its pieces
+    M_out = np.zeros_like(Q)
+    np.add.at(M_out, lr, alpha[:, None] * aV[colidx])
+    M_dQ = np.zeros_like(Q)
+    np.add.at(M_dQ, lr, dem[:, None] * np.abs(Kf)[colidx])
+    M_dK = np.zeros_like(Kf)
+    np.add.at(M_dK, colidx, dem[:, None] * np.abs(Q)[lr])
+    M_dV = np.zeros_like(V)
+    np.add.at(M_dV, colidx, alpha[:, None] * np.abs(dout)[lr])
+    return M_out, M_dQ, M_dK, M_dV
+
+
+def test_attention_backward_fd_instance():
+    spc, ag = _mods()
+    n, nnz, K = 256, 2000, 8
+    rows, cols = synth.uniform_block(n, n, nnz, 4242)
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               (0, n), (0, n), spc.BUILD_CSC)
+    ref = oracle.relabel(rows, cols, (0, n), (0, n))
+    R, C = plan.R, plan.C
+    Q = synth.dense_f32(11, 0, R, K)
+    Kf = synth.dense_f32(12, 0, C, K)
+    V = synth.dense_f32(13, 0, C, K)
+    W = synth.dense_f32(14, 0, R, K)
+    tq = torch.from_numpy(Q).to(DEV).requires_grad_()
+    tk = torch.from_numpy(Kf).to(DEV).requires_grad_()
+    tv = torch.from_numpy(V).to(DEV).requires_grad_()
+    out = ag.gnn_attention(plan, tq, tk, tv)
+    (out * torch.from_numpy(W).to(DEV)).sum().backward()
+    Qd, Kd, Vd, Wd = (x.astype(np.float64) for x in (Q, Kf, V, W))
+    e, alpha, o = oracle.attention_fwd(ref["rowptr"], ref["colidx"], Qd, Kd, Vd)
+    de, dQ, dK, dV = oracle.attention_bwd(ref["rowptr"], ref["colidx"], Qd, Kd, Vd, alpha, Wd)
+    M_out, M_dQ, M_dK, M_dV = _attention_magnitudes(ref["rowptr"], ref["colidx"], Qd, Kd, Vd,
+                                                    alpha, Wd, de)
+    assert_within_mag(_np(out), o, M_out, TOL, "attention out")
+    assert_within_mag(_np(tq.grad), dQ, M_dQ, TOL, "dQ")
+    assert_within_mag(_np(tk.grad), dK, M_dK, TOL, "dKf")
+    assert_within_mag(_np(tv.grad), dV, M_dV, TOL, "dV")
+
+    # central finite differences of the FP64 oracle forward at sampled coordinates
+    def loss(q, k, v):
+        return float((oracle.attention_fwd(ref["rowptr"], ref["colidx"], q, k, v)[2] * Wd).sum())
+
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for X, G, which in ((Qd, tq.grad, 0), (Kd, tk.grad, 1), (Vd, tv.grad, 2)):
+        g = _np(G)
+        scale = np.abs(g).max()
+        for _ in range(25):
+            idx = (int(rng.integers(X.shape[0])), int(rng.integers(X.shape[1])))
+            args_p = [Qd.copy(), Kd.copy(), Vd.copy()]
+            args_m = [Qd.copy(), Kd.copy(), Vd.copy()]
+            args_p[which][idx] += h
+            args_m[which][idx] -= h
+            fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
+            assert abs(g[idx] - fd) <= 1e-4 * scale, (which, idx, g[idx], fd)
+
+
+def test_sddmm_spmm_gather_gradients_with_values():
+    spc, ag = _mods()
+    p = synth.small_rmat(11, 8, 16, 99, row_range=(1 << 10, 1 << 11), col_range=(0, 1 << 10))
+    k0, kz = 4, 8
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range)
+    perm = ref["perm"]
+    As = torch.from_numpy(p.A_src).to(DEV).requires_grad_()
+    Bs = torch.from_numpy(p.B_src).to(DEV).requires_grad_()
+    vals = torch.from_numpy(p.vals[perm]).to(DEV).requires_grad_()
+    W1 = synth.uniform_f32(501, plan.nnz)           # weights of the SDDMM output (slot order)
+    W2 = synth.dense_f32(502, 0, plan.R, kz)        # weights of the SpMM output
+    A = ag.gather(plan, spc.ROWS, As, k0, kz)
+    B = ag.gather(plan, spc.COLS, Bs, k0, kz)
+    c = ag.sddmm(plan, vals, A, B)
+    y = ag.spmm(plan, vals, B, 0)
+    loss = (c * torch.from_numpy(W1).to(DEV)).sum() + (y * torch.from_numpy(W2).to(DEV)).sum()
+    loss.backward()
+    # chain rule written out with the oracle (caller order): let w1 be W1 in caller order
+    w1 = np.empty(plan.nnz, np.float32)
+    w1[perm] = W1
+    ro, co, lo_r, lo_c = p.rows, p.cols, p.row_range[0], p.col_range[0]
+    dot, mdot = oracle.sddmm(ro, co, lo_r, lo_c, None, p.A_src, p.B_src, k0, kz)
+    # d vals_p = W1_p <a,b> + <W2_row, b>
+    lmap_r = ref["lmap_r"]
+    w2dot = (W2.astype(np.float64)[lmap_r[ro - lo_r]] *
+             p.B_src.astype(np.float64)[co - lo_c, k0:k0 + kz]).sum(1)
+    want_dv = w1 * dot + w2dot
+    mag_dv = np.abs(w1) * mdot + (np.abs(W2.astype(np.float64)[lmap_r[ro - lo_r]]) *
+                                  np.abs(p.B_src[co - lo_c, k0:k0 + kz])).sum(1)
+    assert_within_mag(_np(vals.grad)[np.argsort(perm)], want_dv, mag_dv, TOL, "dvals")
+    # dA_src rows: SpMM of (W1 o s) with B, scattered into the K-slice
+    sw = (w1 * p.vals).astype(np.float32)
+    ya, ma = oracle.spmm(ro, co, lo_r, lo_c, lmap_r, ref["R"], sw, p.B_src, k0, kz)
+    gA = _np(As.grad)
+    assert np.all(gA[:, :k0] == 0) and np.all(gA[:, k0 + kz:] == 0)
+    assert_within_mag(gA[ref["gmap_r"] - lo_r, k0:k0 + kz], ya, ma, TOL, "dA_src")
+    # dB_src: SpMM^T of (W1 o s) with A plus SpMM^T of s with W2
+    lmap_c = ref["lmap_c"]
+    yb1, mb1 = oracle.spmm(co, ro, lo_c, lo_r, lmap_c, ref["C"], sw, p.A_src, k0, kz)
+    W2full = np.zeros_like(p.A_src)
+    W2full[ref["gmap_r"] - lo_r, k0:k0 + kz] = W2
+    yb2, mb2 = oracle.spmm(co, ro, lo_c, lo_r, lmap_c, ref["C"], p.vals, W2full, k0, kz)
+    gB = _np(Bs.grad)
+    assert_within_mag(gB[ref["gmap_c"] - lo_c, k0:k0 + kz], yb1 + yb2, mb1 + mb2, TOL, "dB_src")
+
+
+def _rows_subset(rowptr, colidx, rows_pick):
+    """CSR of the picked rows (all their entries) with compacted column ids."""
+    starts, ends = rowptr[rows_pick], rowptr[rows_pick + 1]
+    cnt = ends - starts
+    sub_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    idx = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)])
+    cols = colidx[idx]
+    ucols, inv = np.unique(cols, return_inverse=True)
+    return sub_ptr, inv.astype(np.int32), ucols, idx
+
+
+def test_attention_workload_full_size():
+    """R-MAT 2^20, degree 32, K = 64: forward + backward on the GPU, sampled rows
+    of the output and of dQ against the oracle, forward/backward timings."""
+    spc, ag = _mods()
+    p = synth.attention(dense=False)
+    K = 64
+    _say(f"attention workload nnz={p.nnz}")
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    R, C = plan.R, plan.C
+    Q = synth.dense_f32(21, 0, R, K)
+    Kf = synth.dense_f32(22, 0, C, K)
+    V = synth.dense_f32(23, 0, C, K)
+    W = synth.dense_f32(24, 0, R, K)
+    tq = torch.from_numpy(Q).to(DEV).requires_grad_()
+    tk = torch.from_numpy(Kf).to(DEV).requires_grad_()
+    tv = torch.from_numpy(V).to(DEV).requires_grad_()
+    tw = torch.from_numpy(W).to(DEV)
+    for _ in range(2):   # warm-up
+        out = ag.gnn_attention(plan, tq, tk, tv)
+        (out * tw).sum().backward()
+        tq.grad = tk.grad = tv.grad = None
+    torch.cuda.synchronize()
+    reps = 5
+    t_f = t_b = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = ag.gnn_attention(plan, tq, tk, tv)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (out * tw).sum().backward()
+        torch.cuda.synchronize()
+        t_f += t1 - t0
+        t_b += time.perf_counter() - t1
+        if _ < reps - 1:
+            tq.grad = tk.grad = tv.grad = None
+    m = plan.maps()
+    rowptr, colidx = _np(m["rowptr"]), _np(m["colidx"])
+    rng = np.random.default_rng(3)
+    pick = np.sort(rng.choice(R, size=500, replace=False))
+    sub_ptr, sub_col, ucols, _ = _rows_subset(rowptr, colidx, pick)
+    Qd = Q[pick].astype(np.float64)
+    Kd, Vd = Kf[ucols].astype(np.float64), V[ucols].astype(np.float64)
+    Wd = W[pick].astype(np.float64)
+    e, alpha, o = oracle.attention_fwd(sub_ptr, sub_col, Qd, Kd, Vd)
+    de, dQ, _, _ = oracle.attention_bwd(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd)
+    M_out, M_dQ, _, _ = _attention_magnitudes(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd, de)
+    assert_within_mag(_np(out)[pick], o, M_out, TOL, "attention out (sampled rows)")
+    assert_within_mag(_np(tq.grad)[pick], dQ, M_dQ, TOL, "dQ (sampled rows)")
+    flops = 2 * 2 * K * p.nnz
+    print("ATTENTION_REPORT " + json.dumps({
+        "workload": "rmat20-deg32-whole-K64", "nnz": p.nnz, "R": R, "C": C,
+        "forward_ms": round(t_f / reps * 1e3, 3), "backward_ms": round(t_b / reps * 1e3, 3),
+        "forward_sddmm_spmm_GFLOPs": round(flops / (t_f / reps) / 1e9, 1)}), flush=True)

@@ -354,3 +354,45 @@ def test_attention_backward_finite_differences():
             args_m[which][idx] -= h
             num[idx] = (loss(*args_p) - loss(*args_m)) / (2 * h)
         np.testing.assert_allclose(G, num, rtol=1e-6, atol=1e-8)
+
+
+def test_sddmm_spmm_gradients_by_finite_differences():
+    """The chain-rule identities the backward relies on, pinned by central
+    differences of the oracle forward: d/dA sum(W o SDDMM(S,A,B)) = SpMM(S o W, B)
+    and d/dB sum(W2 o SpMM(S,B)) = SpMM^T(S, W2)."""
+    rows, cols, vals, A, B, rr, cr = _tiny_problem(21, M=9, N=7, K=3, nnz=25)
+    A = A.astype(np.float64).astype(np.float32)
+    lm = oracle.relabel(rows, cols, rr, cr)
+    lmT = oracle.relabel(cols, rows, cr, rr)
+    rng = np.random.default_rng(4)
+    W = rng.standard_normal(rows.size)
+    W2 = rng.standard_normal((lm["R"], 3))
+    h = 1e-3   # loss is linear in A and B: central differences are exact up to rounding
+
+    def f_sddmm(Ax):
+        return float((oracle.sddmm(rows, cols, rr[0], cr[0], vals, Ax, B, 0, 3)[0] * W).sum())
+
+    want, _ = oracle.spmm(rows, cols, rr[0], cr[0], lm["lmap_r"], lm["R"],
+                          (vals * W).astype(np.float32), B, 0, 3)
+    for i, g in enumerate(lm["gmap_r"]):
+        for k in range(3):
+            Ap, Am = A.copy(), A.copy()
+            Ap[g - rr[0], k] += h
+            Am[g - rr[0], k] -= h
+            fd = (f_sddmm(Ap) - f_sddmm(Am)) / (2 * h)
+            assert abs(fd - want[i, k]) <= 1e-4 * (1 + abs(want[i, k]))
+
+    def f_spmm(Bx):
+        y, _ = oracle.spmm(rows, cols, rr[0], cr[0], lm["lmap_r"], lm["R"], vals, Bx, 0, 3)
+        return float((y * W2).sum())
+
+    W2full = np.zeros((rr[1] - rr[0], 3), np.float32)
+    W2full[lm["gmap_r"] - rr[0]] = W2
+    wantB, _ = oracle.spmm(cols, rows, cr[0], rr[0], lmT["lmap_r"], lmT["R"], vals, W2full, 0, 3)
+    for j, g in enumerate(lmT["gmap_r"]):
+        for k in range(3):
+            Bp, Bm = B.copy(), B.copy()
+            Bp[g - cr[0], k] += h
+            Bm[g - cr[0], k] -= h
+            fd = (f_spmm(Bp) - f_spmm(Bm)) / (2 * h)
+            assert abs(fd - wantB[j, k]) <= 1e-4 * (1 + abs(wantB[j, k]))
