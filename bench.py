@@ -97,6 +97,54 @@ def cpu_baseline(p, budget_s=12.0):
                        f"{t_step * 1e3:.1f} ms per step; oracle localization {t_setup:.2f} s")}
 
 
+ERROR_BARS = {
+    "f32": "|x - x*| <= 1e-5 M elementwise vs the FP64 oracle (M = sum of |terms|)",
+    "bf16": "|x - x*| <= (2^-7 + 2^-16 + 1e-5) M vs the FP64 oracle on the FP32 inputs; "
+            "<= 1e-5 M vs the oracle on the BF16-rounded inputs",
+}
+SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2404_19638_amd", "selector_weights.json")
+
+
+def forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_main, per_main, flops):
+    """The plain FP32 form against BF16 operands and the learned selector's
+    variants, each timed like the main loop on the same block."""
+    import torch
+
+    sel = None
+    if os.path.exists(SELECTOR_WEIGHTS):
+        from paper_2404_19638_amd.selector import Selector, load_weights
+        sel = Selector.from_state(load_weights(SELECTOR_WEIGHTS), plan.ws.device)
+    out = {}
+    for dt in ("f32", "bf16"):
+        code = spc.F32 if dt == "f32" else spc.BF16
+        entries = [("default", -1, "library default shape")]
+        if sel is not None:
+            tdt = torch.float32 if dt == "f32" else torch.bfloat16
+            A = torch.rand((plan.R, kz), device=plan.ws.device).to(tdt)
+            B = torch.rand((plan.C, kz), device=plan.ws.device).to(tdt)
+            if args.fused:
+                v, src = sel.choose(plan, "sddmm_spmm", kz, code, A=A, B=B)
+            else:
+                v1, s1 = sel.choose(plan, "sddmm", kz, code, A=A, B=B)
+                v2, s2 = sel.choose(plan, "spmm", kz, code, A=A, B=B)
+                v, src = (v1, v2), f"{s1}/{s2}"
+            entries.append(("learned", v, f"selector ({src})"))
+        for tag, v, how in entries:
+            if dt == args.dtype and v == args.variant:
+                ms, per = ms_main, per_main
+            else:
+                ms, per = timed(make_step(dt, v), args.steps, args.warmup)
+            dom = max(names, key=lambda n: per[n])
+            out[f"{dt}_{tag}"] = {"variant": list(v) if isinstance(v, tuple) else v,
+                                  "chosen_by": how, "ms_per_step": round(ms, 5),
+                                  "value": round(flops / (ms * 1e-3) / 1e9, 2),
+                                  "compute_kernel_ms": round(per[names[2]], 5)
+                                  if len(names) == 4 else
+                                  round(per[names[2]] + per[names[3]], 5),
+                                  "dominant": dom, "error_bar": ERROR_BARS[dt]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +153,8 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the BF16 and learned-selector forms")
     ap.add_argument("--seed", type=int, default=2405)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
@@ -152,54 +202,63 @@ def main():
     R, C, nnz, kz, k0 = plan.R, plan.C, plan.nnz, p.kz, p.k0
     log(f"bench: plan R={R} C={C} nnz={nnz} setup {setup_ms:.1f} ms")
 
-    pdt = torch.float32 if args.dtype == "f32" else torch.bfloat16
-    b = 4 if args.dtype == "f32" else 2
-    A_loc = torch.empty((R, kz), dtype=pdt, device=dev)
-    B_loc = torch.empty((C, kz), dtype=pdt, device=dev)
-    out = torch.empty(nnz, device=dev)
-    Y_loc = torch.empty((R, kz), device=dev)
-    spbuf = torch.empty(spc.spmm_buffer_size(plan, 0, kz, args.variant), dtype=torch.uint8,
-                        device=dev)
     if args.fused:
         names = ["gather_A", "gather_B", "sddmm_spmm", "scatter"]
     else:
         names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
 
-    def step(ev=None):
-        def mark(i):
-            if ev is not None:
-                ev[i].record()
-        mark(0)
-        spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
-        mark(1)
-        spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
-        mark(2)
-        if args.fused:
-            spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=args.variant,
-                           buf=spbuf)
-            mark(3)
-        else:
-            spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=args.variant)
-            mark(3)
-            spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=args.variant, buf=spbuf)
-            mark(4)
-        spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
-        mark(len(names))
+    def make_step(dtype, variant):
+        """One step in dtype; variant is an int, or (SDDMM, SpMM) variants when unfused."""
+        v_sd, v_sp = variant if isinstance(variant, tuple) else (variant, variant)
+        pdt = torch.float32 if dtype == "f32" else torch.bfloat16
+        A_loc = torch.empty((R, kz), dtype=pdt, device=dev)
+        B_loc = torch.empty((C, kz), dtype=pdt, device=dev)
+        out = torch.empty(nnz, device=dev)
+        Y_loc = torch.empty((R, kz), device=dev)
+        spbuf = torch.empty(spc.spmm_buffer_size(plan, 0, kz, v_sp), dtype=torch.uint8,
+                            device=dev)
 
-    for _ in range(args.warmup):
-        step()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
-              for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / args.steps
-    per_kernel_ms = {n: float(np.mean([events[i][j].elapsed_time(events[i][j + 1])
-                                       for i in range(args.steps)]))
-                     for j, n in enumerate(names)}
+        def step(ev=None):
+            def mark(i):
+                if ev is not None:
+                    ev[i].record()
+            mark(0)
+            spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
+            mark(1)
+            spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
+            mark(2)
+            if args.fused:
+                spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=v_sp,
+                               buf=spbuf)
+                mark(3)
+            else:
+                spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=v_sd)
+                mark(3)
+                spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=v_sp, buf=spbuf)
+                mark(4)
+            spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
+            mark(len(names))
+        return step
+
+    def timed(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+                  for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(events[i])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        per = {n: float(np.mean([events[i][j].elapsed_time(events[i][j + 1])
+                                 for i in range(steps)]))
+               for j, n in enumerate(names)}
+        return ms, per
+
+    b = 4 if args.dtype == "f32" else 2
+    ms_per_step, per_kernel_ms = timed(make_step(args.dtype, args.variant), args.steps,
+                                       args.warmup)
     flops = 4.0 * kz * nnz
     value = flops / (ms_per_step * 1e-3) / 1e9
     alg = algorithmic_bytes(R, C, nnz, kz, b)
@@ -211,7 +270,7 @@ def main():
                    "GB_s": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9, 1),
                    "frac_hbm": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for n in names}
-    total_alg = sum(alg.values())
+    total_alg = sum(alg[n] for n in names)
     res = {
         "metric": "SDDMM+SpMM GFLOP/s",
         "value": round(value, 2),
@@ -238,6 +297,9 @@ def main():
         "setup_ms": round(setup_ms, 2),
         "source_hash": src_hash,
     }
+    if not args.no_forms:
+        res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_per_step,
+                             per_kernel_ms, flops)
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
         res["cpu_baseline"] = cpu_baseline(p)

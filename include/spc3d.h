@@ -228,6 +228,79 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan plan, const float* d_alpha, const 
 spc3d_status spc3d_mul_values(spc3d_plan plan, const float* d_a, const float* d_b, float* d_out,
                               hipStream_t stream);
 
+/* ------------------------------------- learned variant selector (ext.) */
+
+/* Operations a variant is chosen for: spc3d_sddmm, spc3d_spmm (transpose 0)
+ * and spc3d_sddmm_spmm. */
+enum { SPC3D_OP_SDDMM = 0, SPC3D_OP_SPMM = 1, SPC3D_OP_SDDMM_SPMM = 2 };
+
+/* Host-only: SPC3D_OK when `variant` (or -1, the default shape) can run
+ * operation `op` on 16-byte aligned packed operands of type ab_t with this
+ * kz; SPC3D_ERR_UNSUPPORTED when the shape does not fit kz (too few lanes, or
+ * too few slots per lane group for SpMM); SPC3D_ERR_INVALID_ARG for a
+ * malformed variant, op, dtype or kz.  Launches nothing. */
+spc3d_status spc3d_variant_check(int op, int32_t kz, spc3d_dtype ab_t, int variant);
+
+/* Number of features spc3d_plan_features writes, and the device scratch
+ * (8-byte aligned) it needs. */
+#define SPC3D_NFEAT 23
+#define SPC3D_FEATURES_BUFFER_BYTES 256
+
+/* Sparsity features of one orientation of a plan (transpose 0: rows of the
+ * CSR view; 1: columns, needs SPC3D_BUILD_CSC), for an operation on packed
+ * operands of type ab_t with K-slice kz.  d_out[SPC3D_NFEAT] (FP32, device):
+ *   [0,16)  fraction of the nnz entries that lie in rows whose length is in
+ *           [2^b, 2^(b+1)) (b = 15 also takes every longer row)
+ *   16 log2(longest row)/16   17 log2(rows)/16   18 log2(columns)/16
+ *   19 log2(nnz)/24           20 log2(nnz/rows)/8
+ *   21 log2(kz)/8             22 1 for BF16 operands, 0 for FP32
+ * (log2 of a value below 1 is taken as 0).  Integer counts are exact; each
+ * fraction is the FP64 quotient rounded to FP32.  d_buf holds
+ * SPC3D_FEATURES_BUFFER_BYTES bytes of scratch. */
+spc3d_status spc3d_plan_features(spc3d_plan plan, int transpose, int32_t kz, spc3d_dtype ab_t,
+                                 float* d_out, void* d_buf, size_t buf_bytes, hipStream_t stream);
+
+/* Dense layer of the selector's multilayer perceptron (FP32, device arrays,
+ * row-major): Y[n x fout] = act(X[n x fin] W[fout x fin]^T + b[fout]), act the
+ * identity (relu = 0) or max(0, .) (relu = 1).  d_b may be NULL (no bias).
+ * Limits: 1 <= fin, fout <= 1024, 0 <= n <= 2^20, n * max(fin, fout) <=
+ * 65535 * 256.  Y may not alias X. */
+spc3d_status spc3d_mlp_linear_fwd(int n, int fin, int fout, const float* d_X, const float* d_W,
+                                  const float* d_b, float* d_Y, int relu, hipStream_t stream);
+
+/* Bytes of scratch spc3d_mlp_linear_bwd needs for (n, fin, fout). */
+spc3d_status spc3d_mlp_linear_bwd_buffer_size(int n, int fin, int fout, size_t* bytes);
+
+/* Backward of spc3d_mlp_linear_fwd given the upstream gradient dY [n x fout]:
+ * with G = dY masked by Y > 0 when relu = 1 (the derivative at 0 taken as 0),
+ *   dX = G W (skipped when d_dX is NULL),  dW = G^T X,  db = column sums of G
+ * (skipped when d_db is NULL).  d_Y is the forward output (read only when
+ * relu = 1).  Reductions over n run in a fixed order (deterministic).  d_buf
+ * (4-byte aligned) holds spc3d_mlp_linear_bwd_buffer_size bytes. */
+spc3d_status spc3d_mlp_linear_bwd(int n, int fin, int fout, const float* d_X, const float* d_W,
+                                  const float* d_Y, const float* d_dY, int relu, float* d_dX,
+                                  float* d_dW, float* d_db, void* d_buf, size_t buf_bytes,
+                                  hipStream_t stream);
+
+/* Masked mean squared error over n entries: with c = sum mask (1 if 0),
+ *   loss = sum mask (P - T)^2 / c,   dP = 2 mask (P - T) / c.
+ * d_loss (one float) may be NULL.  One workgroup; fixed summation order. */
+spc3d_status spc3d_mlp_mse(int64_t n, const float* d_P, const float* d_T, const float* d_mask,
+                           float* d_dP, float* d_loss, hipStream_t stream);
+
+/* One Adam step (Kingma and Ba, 2015) at step count `step` >= 1 on n
+ * parameters w with gradient g and moment estimates m, v (updated in place):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   w -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+spc3d_status spc3d_mlp_adam(int64_t n, float* d_w, const float* d_g, float* d_m, float* d_v,
+                            float lr, float beta1, float beta2, float eps, int step,
+                            hipStream_t stream);
+
+/* idx[r] = the least-P column o among those with mask[r*m + o] != 0 (the
+ * first on ties), -1 when a row has none; P and mask [n x m] FP32. */
+spc3d_status spc3d_mlp_masked_argmin(int n, int m, const float* d_P, const float* d_mask,
+                                     int32_t* d_idx, hipStream_t stream);
+
 /* ----------------------------------------------------------- diagnostics */
 
 const char* spc3d_status_string(spc3d_status status);

@@ -164,4 +164,12 @@ spc3d_status spc3d_sddmm_spmm(spc3d_plan h, const float* d_vals, const void* d_A
                   d_out);
 }
 
+spc3d_status spc3d_variant_check(int op, int32_t kz, spc3d_dtype ab_t, int variant) {
+  if (op < SPC3D_OP_SDDMM || op > SPC3D_OP_SDDMM_SPMM) return fail(SPC3D_ERR_INVALID_ARG, "bad op %d", op);
+  if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  Shape sh;
+  return pick_shape(kz, ab_t, true, variant, op, &sh);
+}
+
 }  // extern "C"

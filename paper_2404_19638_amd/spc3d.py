@@ -22,6 +22,9 @@ ROWS, COLS = 0, 1
 OVERWRITE, ACCUMULATE = 0, 1
 BUILD_CSC = 1
 CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
+OP_SDDMM, OP_SPMM, OP_SDDMM_SPMM = 0, 1, 2
+NFEAT = 23
+FEATURES_BUFFER_BYTES = 256
 
 
 def variant(lg_lanes: int, lg_items: int, wide: int = 0) -> int:
@@ -68,6 +71,15 @@ def lib():
         "spc3d_row_softmax": [vp, vp, vp, vp, sz, vp],
         "spc3d_row_softmax_bwd": [vp, vp, vp, vp, vp, sz, vp],
         "spc3d_mul_values": [vp, vp, vp, vp, vp],
+        "spc3d_variant_check": [ctypes.c_int, i32, ctypes.c_int, ctypes.c_int],
+        "spc3d_plan_features": [vp, ctypes.c_int, i32, ctypes.c_int, vp, vp, sz, vp],
+        "spc3d_mlp_linear_fwd": [ctypes.c_int] * 3 + [vp] * 4 + [ctypes.c_int, vp],
+        "spc3d_mlp_linear_bwd_buffer_size": [ctypes.c_int] * 3 + [P(sz)],
+        "spc3d_mlp_linear_bwd": [ctypes.c_int] * 3 + [vp] * 4 + [ctypes.c_int] + [vp] * 4
+                                + [sz, vp],
+        "spc3d_mlp_mse": [i64, vp, vp, vp, vp, vp, vp],
+        "spc3d_mlp_adam": [i64, vp, vp, vp, vp] + [ctypes.c_float] * 4 + [ctypes.c_int, vp],
+        "spc3d_mlp_masked_argmin": [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -348,4 +360,114 @@ def mul_values(plan: Plan, a: torch.Tensor, b: torch.Tensor, out=None, stream=No
     out = torch.empty_like(a) if out is None else out
     _check(lib().spc3d_mul_values(plan.handle, _ptr(a), _ptr(b), _ptr(out), _stream(stream)),
            "spc3d_mul_values")
+    return out
+
+
+# ------------------------------------------------- learned variant selector
+
+def variant_check(op: int, kz: int, dtype: int, variant: int) -> int:
+    """Status of spc3d_variant_check (OK, ERR_UNSUPPORTED or ERR_INVALID_ARG); no launch."""
+    return lib().spc3d_variant_check(op, kz, dtype, variant)
+
+
+def plan_features(plan: Plan, kz: int, dtype: int, transpose: int = 0, out=None, stream=None):
+    """SPC3D_NFEAT FP32 sparsity features of the plan (device tensor)."""
+    dev = plan.ws.device
+    if out is None:
+        out = torch.empty(NFEAT, dtype=torch.float32, device=dev)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= NFEAT,
+          "out must hold NFEAT FP32 values")
+    buf = plan.buffer("features", FEATURES_BUFFER_BYTES)
+    _check(lib().spc3d_plan_features(plan.handle, transpose, kz, dtype, _ptr(out), _ptr(buf),
+                                     buf.numel(), _stream(stream)), "spc3d_plan_features")
+    return out
+
+
+def _f32_2d(t, rows, cols, name):
+    _need(t.dtype == torch.float32 and t.is_contiguous() and t.numel() >= rows * cols,
+          f"{name} must be a contiguous FP32 [{rows} x {cols}] tensor")
+
+
+def mlp_linear_fwd(X: torch.Tensor, W: torch.Tensor, b=None, relu: bool = False, out=None,
+                   stream=None):
+    n, fin = X.shape
+    fout = W.shape[0]
+    _f32_2d(X, n, fin, "X")
+    _f32_2d(W, fout, fin, "W")
+    _need(W.shape[1] == fin, "W must be [fout x fin]")
+    _need(b is None or (b.dtype == torch.float32 and b.numel() == fout), "b must hold fout values")
+    if out is None:
+        out = torch.empty((n, fout), dtype=torch.float32, device=X.device)
+    _f32_2d(out, n, fout, "out")
+    _check(lib().spc3d_mlp_linear_fwd(n, fin, fout, _ptr(X), _ptr(W), _ptr(b), _ptr(out),
+                                      int(relu), _stream(stream)), "spc3d_mlp_linear_fwd")
+    return out
+
+
+def mlp_linear_bwd_buffer_size(n: int, fin: int, fout: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_mlp_linear_bwd_buffer_size(n, fin, fout, ctypes.byref(b)),
+           "spc3d_mlp_linear_bwd_buffer_size")
+    return b.value
+
+
+def mlp_linear_bwd(X, W, Y, dY, relu: bool = False, need_dx: bool = True, dX=None, dW=None,
+                   db=None, buf=None, stream=None):
+    """Returns (dX or None, dW, db) of mlp_linear_fwd."""
+    n, fin = X.shape
+    fout = W.shape[0]
+    _f32_2d(X, n, fin, "X")
+    _f32_2d(W, fout, fin, "W")
+    _f32_2d(dY, n, fout, "dY")
+    _need(not relu or Y is not None, "Y is needed with relu")
+    if relu:
+        _f32_2d(Y, n, fout, "Y")
+    dev = X.device
+    if need_dx and dX is None:
+        dX = torch.empty((n, fin), dtype=torch.float32, device=dev)
+    if dW is None:
+        dW = torch.empty((fout, fin), dtype=torch.float32, device=dev)
+    if db is None:
+        db = torch.empty(fout, dtype=torch.float32, device=dev)
+    need = mlp_linear_bwd_buffer_size(n, fin, fout)
+    if buf is None or buf.numel() < need:
+        buf = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().spc3d_mlp_linear_bwd(n, fin, fout, _ptr(X), _ptr(W), _ptr(Y if relu else None),
+                                      _ptr(dY), int(relu), _ptr(dX if need_dx else None),
+                                      _ptr(dW), _ptr(db), _ptr(buf), buf.numel(),
+                                      _stream(stream)), "spc3d_mlp_linear_bwd")
+    return (dX if need_dx else None), dW, db
+
+
+def mlp_mse(P, T, M, dP=None, loss=None, stream=None):
+    """Masked mean squared error; returns (loss [1] device tensor, dP)."""
+    n = P.numel()
+    for t, name in ((P, "P"), (T, "T"), (M, "M")):
+        _need(t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n,
+              f"{name} must be contiguous FP32 with {n} values")
+    dP = torch.empty_like(P) if dP is None else dP
+    loss = torch.empty(1, dtype=torch.float32, device=P.device) if loss is None else loss
+    _check(lib().spc3d_mlp_mse(n, _ptr(P), _ptr(T), _ptr(M), _ptr(dP), _ptr(loss),
+                               _stream(stream)), "spc3d_mlp_mse")
+    return loss, dP
+
+
+def mlp_adam(w, g, m, v, lr: float, beta1: float, beta2: float, eps: float, step: int,
+             stream=None):
+    n = w.numel()
+    for t, name in ((w, "w"), (g, "g"), (m, "m"), (v, "v")):
+        _need(t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n,
+              f"{name} must be contiguous FP32 with {n} values")
+    _check(lib().spc3d_mlp_adam(n, _ptr(w), _ptr(g), _ptr(m), _ptr(v), lr, beta1, beta2, eps,
+                                step, _stream(stream)), "spc3d_mlp_adam")
+    return w
+
+
+def mlp_masked_argmin(P, M, out=None, stream=None):
+    n, m = P.shape
+    _f32_2d(P, n, m, "P")
+    _f32_2d(M, n, m, "M")
+    out = torch.empty(n, dtype=torch.int32, device=P.device) if out is None else out
+    _check(lib().spc3d_mlp_masked_argmin(n, m, _ptr(P), _ptr(M), _ptr(out), _stream(stream)),
+           "spc3d_mlp_masked_argmin")
     return out

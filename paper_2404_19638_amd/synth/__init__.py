@@ -18,6 +18,14 @@ Workload recipes
 ``precision`` R-MAT on 2^22 vertices, 2^27 samples (average degree 32), the
               whole matrix as one block, K=128.
 ``attention`` R-MAT on 2^20 vertices, 2^25 samples, K=64.
+``selector``  512 square blocks n x n for training and judging the learned
+              variant selector: n = round(2^(10 + 8u)) (log-uniform in
+              [2^10, 2^18]), target average degree 4 * 16^v (log-uniform in
+              [4, 64]), u and v counter draws; even blocks take uniform
+              positions (round(deg * n) distinct entries), odd blocks R-MAT on
+              2^ceil(log2 n) vertices, permuted, keeping the ids below n, with
+              deg * n * (2^s / n)^2 samples so that about deg * n land in the
+              block before de-duplication.  Split 384 / 128 by block.
 """
 from __future__ import annotations
 
@@ -207,3 +215,40 @@ def small_rmat(scale: int, deg: int, K: int, seed: int, row_range=None, col_rang
     vals = uniform_f32(seed + 7, rows.shape[0])
     A, B = _dense_pair(seed, rr, cr, K)
     return Problem("small_rmat", rows, cols, vals, rr, cr, A, B, K, 0, K, seed)
+
+
+SELECTOR_SEED = 2408
+
+
+def _unit(seed: int, ctr: int) -> float:
+    """Counter draw mapped to [0, 1) with 53 bits."""
+    return (draw(seed, ctr) >> 11) * (1.0 / (1 << 53))
+
+
+def selector_block(i: int, seed: int = SELECTOR_SEED, lg_lo: float = 10.0, lg_hi: float = 18.0,
+                   deg_lo: float = 4.0, deg_hi: float = 64.0) -> dict:
+    """Block i of the selector workload (see the module docstring).
+
+    Returns dict(i, kind, n, deg, rows, cols): int64 ids in [0, n), caller order.
+    """
+    u = _unit(seed, 4 * i)
+    v = _unit(seed, 4 * i + 1)
+    n = int(round(2.0 ** (lg_lo + (lg_hi - lg_lo) * u)))
+    deg = deg_lo * (deg_hi / deg_lo) ** v
+    bseed = draw(seed, 4 * i + 2) & ((1 << 62) - 1)
+    if i % 2 == 0:
+        kind = "uniform"
+        nnz = min(int(round(deg * n)), n * n // 2)
+        rows, cols = uniform_block(n, n, nnz, bseed)
+    else:
+        kind = "rmat"
+        s = max(1, (n - 1).bit_length())
+        samples = int(round(deg * n * ((1 << s) / n) ** 2))
+        rows, cols = rmat_block(s, samples, bseed, (0, n), (0, n))
+    return dict(i=i, kind=kind, n=n, deg=deg, rows=rows, cols=cols)
+
+
+def selector_split(nblocks: int = 512, ntrain: int = 384, seed: int = SELECTOR_SEED):
+    """Seeded split of block indices into (train, held_out), both ascending."""
+    order = sorted(range(nblocks), key=lambda i: (draw(seed + 1, i), i))
+    return sorted(order[:ntrain]), sorted(order[ntrain:])
