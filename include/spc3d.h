@@ -75,9 +75,13 @@ enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
 
 /* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose;
  * otherwise (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64,
- * 0..4) << 4 | (SpMM gathers 16 rows per batch instead of 8, 0..1) << 8.
- * Every valid variant computes the same result within the stated tolerance. */
+ * 0..4) << 4 | (SpMM gathers 16 rows per batch instead of 8, 0..1) << 8 |
+ * SPC3D_VARIANT_WINDOW for the windowed SpMM family (each 64-slot window's
+ * rows in flight together, row sums by a segmented scan; 2, 4 or 8 lanes,
+ * not combined with the 16-row batches).  The SDDMM kernel ignores bits 8 and 9.  Every valid
+ * variant computes the same result within the stated tolerance. */
 #define SPC3D_VARIANT(lg_lanes, lg_items, wide) ((lg_lanes) | ((lg_items) << 4) | ((wide) << 8))
+#define SPC3D_VARIANT_WINDOW 0x200
 
 typedef struct spc3d_plan_s* spc3d_plan;
 

@@ -30,7 +30,7 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
     return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes,
                 (size_t)nitems * 2 * (size_t)kz * 4);
-  const size_t lds = 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec, fused);
+  const size_t lds = sh.window ? 0 : 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec, fused);
   if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
   st = use_device(p);
   if (st != SPC3D_OK) return st;

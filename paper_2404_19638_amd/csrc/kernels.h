@@ -211,10 +211,14 @@ __device__ inline void zero(float (&acc)[NCH][VEC]) {
 // LDS bytes one wavefront of k_spmm uses (fused: plus the SDDMM outputs).
 // Staged per-slot arrays hold one pad word per run of S = W/G slots, so the
 // G groups reading slot u of their runs hit different LDS banks.
-inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec, bool fused) {
+// The item's head words and tile rows (12 bytes per 64 slots) are staged too,
+// so no batch waits on a global load before it can address its rows.
+__host__ __device__ inline size_t spmm_wave_lds(int wslots, int lpn, int nch, int vec, bool fused) {
   const int G = 64 / lpn;
   const size_t P = (size_t)wslots + G;
-  return P * (fused ? 12 : 8) + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4;
+  const size_t bytes = P * (fused ? 12 : 8) + (size_t)G * lpn * nch * vec * 4 + (size_t)G * 4 +
+                       (size_t)(wslots / 64) * 12;
+  return (bytes + 15) & ~(size_t)15;   // keeps every wave's 8-byte head words aligned
 }
 
 // One batch of UB consecutive slots of a group: their columns, values, head
@@ -231,16 +235,16 @@ struct Batch {
 template <typename T, int VEC, int LPN, int NCH, int UB, bool FUSED>
 __device__ inline void load_batch(Batch<T, VEC, LPN, NCH, UB, FUSED>& bt, int64_t s0, int64_t b,
                                   int64_t ge, const int* s_col, const float* s_val,
-                                  const uint64_t* __restrict__ head,
-                                  const int32_t* __restrict__ tile_row, const T* __restrict__ X,
-                                  const T* __restrict__ A, int kz, int q, int nvec, int64_t gs,
-                                  int lgS) {
+                                  const uint64_t* s_head, const int* s_trow,
+                                  const T* __restrict__ X, const T* __restrict__ A, int kz, int q,
+                                  int nvec, int64_t gs, int lgS) {
   const bool any = s0 < ge;
   const int64_t sw = any ? s0 : b;   // a valid slot for the head word
-  const uint64_t hw = head[sw >> 6];
+  const int wi = (int)((sw - b) >> 6);
+  const uint64_t hw = s_head[wi];
   bt.hbits = (unsigned)(hw >> (sw & 63)) & ((1u << UB) - 1u);
   int rbase = 0;
-  if constexpr (FUSED) rbase = tile_row[sw >> 6] + __popcll(hw & lanemask_le((int)(sw & 63)) & ~1ull);
+  if constexpr (FUSED) rbase = s_trow[wi] + __popcll(hw & lanemask_le((int)(sw & 63)) & ~1ull);
 #pragma unroll
   for (int u = 0; u < UB; ++u) {
     const bool ok = s0 + u < ge;
@@ -285,13 +289,18 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / LPN, q = lane % LPN;
   const size_t P = (size_t)wslots + G;   // staged slots plus one pad word per run
-  const size_t wave_bytes = P * (FUSED ? 12 : 8) + (size_t)G * KW * 4 + (size_t)G * 4;
+  const int nwords = wslots / 64;
+  const size_t wave_bytes = spmm_wave_lds(wslots, LPN, NCH, VEC, FUSED);
   char* wbase = smem + (size_t)wv * wave_bytes;
-  int* s_col = reinterpret_cast<int*>(wbase);
-  float* s_val = reinterpret_cast<float*>(wbase + P * 4);
-  float* s_out = reinterpret_cast<float*>(wbase + P * 8);   // FUSED only
-  float* s_lead = reinterpret_cast<float*>(wbase + P * (FUSED ? 12 : 8));
-  int* s_kind = reinterpret_cast<int*>(wbase + P * (FUSED ? 12 : 8) + (size_t)G * KW * 4);
+  // 8-byte head words first (wave_bytes is a multiple of 16)
+  uint64_t* s_head = reinterpret_cast<uint64_t*>(wbase);
+  char* wrest = wbase + (size_t)nwords * 8;
+  int* s_col = reinterpret_cast<int*>(wrest);
+  float* s_val = reinterpret_cast<float*>(wrest + P * 4);
+  float* s_out = reinterpret_cast<float*>(wrest + P * 8);   // FUSED only
+  float* s_lead = reinterpret_cast<float*>(wrest + P * (FUSED ? 12 : 8));
+  int* s_kind = reinterpret_cast<int*>(wrest + P * (FUSED ? 12 : 8) + (size_t)G * KW * 4);
+  int* s_trow = s_kind + G;
 
   const int64_t item = xcd_block(nblocks) * 4 + wv;
   const bool active = item < nitems;
@@ -306,6 +315,11 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
       const int pi = i + (i >> lgS);
       s_col[pi] = idx[b + i];
       s_val[pi] = vals ? vals[vidx ? vidx[b + i] : b + i] : 1.f;
+    }
+    const int nw = (int)((e - b + 63) >> 6);   // b is a multiple of 64
+    for (int i = lane; i < nw; i += 64) {
+      s_head[i] = head[(b >> 6) + i];
+      s_trow[i] = tile_row[(b >> 6) + i];
     }
   }
   __syncthreads();
@@ -323,8 +337,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
     BT cb;
     float acur[FUSED ? NCH : 1][VEC];
     for (int64_t s0 = gs; s0 < ge; s0 += UB) {
-      load_batch<T, VEC, LPN, NCH, UB, FUSED>(cb, s0, b, ge, s_col, s_val, head, tile_row, X, A, kz,
-                                              q, nvec, gs, lgS);
+      load_batch<T, VEC, LPN, NCH, UB, FUSED>(cb, s0, b, ge, s_col, s_val, s_head, s_trow, X, A,
+                                              kz, q, nvec, gs, lgS);
       if constexpr (FUSED) {
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
@@ -411,6 +425,228 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
   }
 }
 
+// ------------------------------------------------- SpMM, windowed family
+//
+// The SDDMM window layout applied to SpMM: in each 64-slot window, group g
+// owns slots g*L .. g*L+L-1 and has all their rows in flight at once (JB per
+// batch), so a wavefront keeps as many rows in flight as the SDDMM kernel
+// and needs no LDS.  Each lane sums s_p * X[col] over the group's slots in
+// slot order; a row that starts and ends inside a group is stored directly.
+// The pieces of rows that cross group boundaries meet in a segmented
+// inclusive scan over the G groups (shuffles, log2 G steps, fixed order);
+// the row running out of a window is carried in registers into the next.
+// Rows cut by work-item boundaries leave head / tail carries for
+// k_spmm_fixup, as the group-run family does.  With FUSED, the same rows
+// also give the SDDMM dots (A rows loaded per slot, as in k_sddmm).
+template <int VEC, int NCH>
+__device__ inline void shfl_vec(const float (&src)[NCH][VEC], float (&dst)[NCH][VEC], int from) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) dst[ch][t] = __shfl(src[ch][t], from);
+}
+
+__device__ inline int win_row(int trow, uint64_t hw, int i) {
+  return trow + __popcll(hw & lanemask_le(i) & ~1ull);
+}
+
+template <typename T, int VEC, int LPN, int NCH, bool FUSED>
+__global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int64_t nblocks,
+                                               int wslots, const int32_t* __restrict__ idx,
+                                               const uint64_t* __restrict__ head,
+                                               const int32_t* __restrict__ tile_row,
+                                               const float* __restrict__ vals,
+                                               const int32_t* __restrict__ vidx,
+                                               const T* __restrict__ X, int kz,
+                                               float* __restrict__ Y, int accumulate,
+                                               float* __restrict__ carry,
+                                               const T* __restrict__ A,
+                                               float* __restrict__ out) {
+  constexpr int G = 64 / LPN;
+  constexpr int JB0 = FUSED ? 64 / (2 * NCH * VEC) : 64 / (NCH * VEC);
+  constexpr int JB = JB0 < 1 ? 1 : (JB0 > LPN ? LPN : JB0);
+  const int lane = threadIdx.x & 63;
+  const int g = lane / LPN, q = lane % LPN;
+  const int64_t item = xcd_block(nblocks) * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;   // uniform per wavefront; no barriers below
+  const int nvec = kz / VEC;
+  const int64_t b = item * wslots;
+  const int64_t e = (b + wslots < nnz) ? b + wslots : nnz;
+  const bool ends_at_e = (e >= nnz) || is_head(head, e);
+  const int gl = g * LPN;
+
+  float cy[NCH][VEC];   // the row running in from the previous window (same in every group)
+  zero(cy);
+  bool cy_own = false;  // that row started inside this item
+  // The next window's indices, values and head word are loaded while the
+  // current window's rows are in flight (one memory round trip per window).
+  int col_n = 0;
+  float v_n = 0.f;
+  uint64_t hw_n = 0;
+  int trow_n = 0;
+  auto fetch = [&](int64_t w0) {
+    const int64_t sl = w0 + lane;
+    const bool ok = sl < e;
+    col_n = ok ? idx[sl] : 0;
+    v_n = ok ? (vals ? vals[vidx ? vidx[sl] : sl] : 1.f) : 0.f;
+    hw_n = head[w0 >> 6];
+    trow_n = tile_row[w0 >> 6];
+  };
+  fetch(b);
+  for (int64_t win = b; win < e; win += 64) {
+    const int nv = (e - win < 64) ? (int)(e - win) : 64;
+    const bool valid = lane < nv;
+    const int64_t sl = win + lane;
+    const int col = col_n;
+    const float v = v_n;
+    uint64_t hw = hw_n;
+    const int trow = trow_n;
+    if (nv < 64) hw &= (1ull << nv) - 1ull;
+    const bool more = win + 64 < e;
+    const bool next_head = more ? (bool)(head[(win >> 6) + 1] & 1ull) : ends_at_e;
+    if (more) fetch(win + 64);
+    const bool g_head = (hw >> gl) & 1ull;
+
+    float acc[NCH][VEC], lp[NCH][VEC];
+    zero(acc);
+    zero(lp);
+    bool first_seg = true, has_lp = false;
+    float res = 0.f;
+#pragma unroll
+    for (int j0 = 0; j0 < LPN; j0 += JB) {
+      float bb[JB][NCH][VEC];
+      float a[FUSED ? JB : 1][NCH][VEC];
+      float sv[JB];
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int src = gl + j0 + jj;
+        const int c = __shfl(col, src);
+        sv[jj] = __shfl(v, src);
+        load_row<T, VEC, LPN, NCH>(X + (int64_t)c * kz, q, nvec, bb[jj]);
+        if constexpr (FUSED)
+          load_row<T, VEC, LPN, NCH>(A + (int64_t)win_row(trow, hw, src) * kz, q, nvec, a[jj]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JB; ++jj) {
+        const int j = j0 + jj, w = gl + j;
+        if constexpr (FUSED) {
+          const float d = group_sum<LPN>(lane_dot<VEC, LPN, NCH>(a[jj], bb[jj], q, nvec));
+          if (q == j) res = d;
+        }
+        // A row starting at slot w ends the segment before it: a row complete
+        // inside the group is stored; the group's first segment, when it began
+        // in an earlier group, is kept for the scan.  Branch-free but the store.
+        const bool in = w < nv;
+        const bool brk = in && j > 0 && ((hw >> w) & 1ull);
+        const bool to_lp = brk && first_seg && !g_head;
+        if (brk && !to_lp)
+          store_row<VEC, NCH>(Y, win_row(trow, hw, w - 1), kz, nvec, q, LPN, acc, accumulate);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+          for (int t = 0; t < VEC; ++t) {
+            lp[ch][t] = to_lp ? acc[ch][t] : lp[ch][t];
+            const float a0 = brk ? 0.f : acc[ch][t];
+            acc[ch][t] = in ? fmaf(sv[jj], bb[jj][ch][t], a0) : a0;
+          }
+        has_lp = has_lp || to_lp;
+        first_seg = first_seg && !brk;
+      }
+    }
+    if constexpr (FUSED) {
+      if (valid) {
+        const float o = v * res;
+        out[sl] = accumulate ? out[sl] + o : o;
+      }
+    }
+
+    // segmented inclusive scan of the groups' last segments
+    bool f = !first_seg || g_head;   // this group's last segment starts in the group
+    bool own = true;
+    if (g == 0 && !f) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) acc[ch][t] = cy[ch][t] + acc[ch][t];
+      own = cy_own;
+      f = true;
+    }
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const int from = g >= d ? lane - d * LPN : lane;
+      float xs[NCH][VEC];
+      shfl_vec<VEC, NCH>(acc, xs, from);
+      const bool fs = __shfl((int)f, from) != 0;
+      const bool os = __shfl((int)own, from) != 0;
+      if (g >= d) {
+        if (!f) {
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) acc[ch][t] = xs[ch][t] + acc[ch][t];
+          own = os;
+        }
+        f = f || fs;
+      }
+    }
+    // the row a group's first segment closes: the scan value of the group before
+    float prev[NCH][VEC];
+    shfl_vec<VEC, NCH>(acc, prev, g > 0 ? lane - LPN : lane);
+    // (every shuffle runs on all 64 lanes: no shuffle reads an inactive lane)
+    const bool own_left = __shfl((int)own, g > 0 ? lane - LPN : lane) != 0;
+    const bool prev_own = g > 0 ? own_left : cy_own;
+    if (g == 0) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) prev[ch][t] = cy[ch][t];
+    }
+    if (has_lp) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) lp[ch][t] = prev[ch][t] + lp[ch][t];
+      if (prev_own)
+        store_row<VEC, NCH>(Y, win_row(trow, hw, gl), kz, nvec, q, LPN, lp, accumulate);
+      else
+        store_vec<VEC, NCH>(carry + (item * 2) * kz, nvec, q, LPN, lp);
+    }
+    // a row ending exactly at the end of a group inside the window
+    const int glast = gl + LPN;
+    if (g < G - 1 && glast < nv && ((hw >> glast) & 1ull)) {
+      if (own)
+        store_row<VEC, NCH>(Y, win_row(trow, hw, glast - 1), kz, nvec, q, LPN, acc, accumulate);
+      else
+        store_vec<VEC, NCH>(carry + (item * 2) * kz, nvec, q, LPN, acc);
+    }
+    // the row at the end of the window
+    float last[NCH][VEC];
+    shfl_vec<VEC, NCH>(acc, last, (G - 1) * LPN + q);
+    const bool last_own = __shfl((int)own, (G - 1) * LPN) != 0;
+    if (next_head || win + 64 >= e) {
+      if (g == 0) {
+        if (next_head) {
+          if (last_own)
+            store_row<VEC, NCH>(Y, win_row(trow, hw, nv - 1), kz, nvec, q, LPN, last, accumulate);
+          else
+            store_vec<VEC, NCH>(carry + (item * 2) * kz, nvec, q, LPN, last);
+        } else {
+          // the item ends inside a row: its owner finishes it in k_spmm_fixup
+          store_vec<VEC, NCH>(carry + (item * 2 + (last_own ? 1 : 0)) * kz, nvec, q, LPN, last);
+        }
+      }
+      zero(cy);
+      cy_own = false;
+    } else {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) cy[ch][t] = last[ch][t];
+      cy_own = last_own;
+    }
+  }
+}
+
 // Rows cut by item boundaries: item j whose last row starts inside it and
 // continues past its end owns the row; it adds its tail carry and the head
 // carries of the items the row runs through, in item order.
@@ -474,6 +710,7 @@ struct Shape {
   int nch;    // vectors per lane
   int items;  // W
   int wide;   // SpMM: batches of up to 16 slots instead of 8
+  int window; // SpMM: the windowed family (k_wspmm) instead of group runs
 };
 
 inline int pow2ceil(int n) {
@@ -504,19 +741,23 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
     sh->items = spmm ? 512 : 64;
     while (spmm && sh->items / (64 / sh->lanes) < 8) sh->items *= 2;
     sh->wide = 0;
+    sh->window = 0;
   } else {
     const int lg = variant & 15, lw = (variant >> 4) & 15;
-    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 9))
+    if (lg < 1 || lg > 6 || lw > 4 || (variant >> 10) || ((variant >> 8) & 3) == 3)
       return fail(SPC3D_ERR_INVALID_ARG, "bad variant %d", variant);
     sh->lanes = 1 << lg;
     sh->items = 64 << lw;
     sh->wide = (variant >> 8) & 1;
+    sh->window = (variant >> 9) & 1;
   }
   sh->nch = (nvec + sh->lanes - 1) / sh->lanes;
   if (sh->nch == 3) sh->nch = 4;
   if (sh->nch > 4)
     return fail(SPC3D_ERR_UNSUPPORTED, "variant has too few lanes for kz=%d", kz);
-  if (spmm) {
+  if (sh->window && spmm && sh->lanes > 8)
+    return fail(SPC3D_ERR_UNSUPPORTED, "the windowed SpMM family takes 2, 4 or 8 lanes");
+  if (spmm && !sh->window) {
     const int G = 64 / sh->lanes;
     if (sh->items / G < (sh->wide ? 16 : 8))
       return fail(SPC3D_ERR_UNSUPPORTED, "SpMM variant needs >= %d slots per group",
@@ -558,7 +799,14 @@ void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, i
                  const Orient& o, const float* vals, const void* X, int kz, float* Y,
                  int accumulate, float* carry, size_t lds, const void* A, float* out) {
   SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
-      if (sh.wide)
+      if (sh.window) {
+        // 2, 4 or 8 lanes (pick_shape); wider groups would unroll too far
+        if constexpr (LPN_ <= 8)
+          hipLaunchKernelGGL((k_wspmm<T, VEC, LPN_, NCH_, FUSED>), dim3((unsigned)nblocks),
+                             dim3(256), 0, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
+                             o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y,
+                             accumulate, carry, static_cast<const T*>(A), out);
+      } else if (sh.wide)
         hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, 16>), dim3((unsigned)nblocks),
                            dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
                            o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,

@@ -119,16 +119,17 @@ class MLP:
         return m
 
 
-def valid_mask(op: str, kz: int, dtype: int) -> np.ndarray:
+def valid_mask(op: str, kz: int, dtype: int, cands=None) -> np.ndarray:
     """1.0 for the candidates of op that can run with (kz, dtype), else 0.0."""
-    return np.array([1.0 if tune.valid(op, kz, dtype, v) else 0.0 for v in tune.candidates(op)],
+    cands = tune.candidates(op) if cands is None else cands
+    return np.array([1.0 if tune.valid(op, kz, dtype, v) else 0.0 for v in cands],
                     dtype=np.float32)
 
 
-def targets(timings: dict, op: str):
+def targets(timings: dict, op: str, cands=None):
     """Training row of one autotune result: (T, M) over the candidates of op,
     T = min(log2(t_v / t_best), TARGET_CAP) where timed, M = 1 there."""
-    cands = tune.candidates(op)
+    cands = tune.candidates(op) if cands is None else cands
     best = min(t for v, t in timings.items() if v in cands)
     T = np.zeros(len(cands), np.float32)
     M = np.zeros(len(cands), np.float32)
@@ -147,6 +148,7 @@ class Selector:
         self.seed = seed
         self.device = torch.device(device)
         self.models = {}
+        self.cands = {}   # op -> candidate variants, one network output each
         self.lo = {}
         self.hi = {}
         self._masks = {}
@@ -154,7 +156,8 @@ class Selector:
     def fit(self, op: str, X: np.ndarray, T: np.ndarray, M: np.ndarray, steps: int = 3000,
             lr: float = 3e-3, lr_final: float = 3e-4, log_every: int = 0, log=None) -> list:
         X = np.asarray(X, np.float32)
-        ncand = len(tune.candidates(op))
+        self.cands[op] = tune.candidates(op)
+        ncand = len(self.cands[op])
         assert X.shape[1] == NFEAT and T.shape[1] == ncand and M.shape == T.shape
         mlp = MLP([NFEAT, *self.hidden, ncand], self.seed + tune.OPCODE[op], self.device)
         dev = self.device
@@ -169,11 +172,12 @@ class Selector:
     def _mask(self, op, kz, dtype):
         key = (op, kz, dtype)
         if key not in self._masks:
-            self._masks[key] = torch.from_numpy(valid_mask(op, kz, dtype)).to(self.device)
+            self._masks[key] = torch.from_numpy(valid_mask(op, kz, dtype, self.cands[op])).to(
+                self.device)
         return self._masks[key]
 
     def predict_indices(self, op: str, X: torch.Tensor, masks: torch.Tensor) -> torch.Tensor:
-        """Per row of X, the index into tune.candidates(op) of the least
+        """Per row of X, the index into self.cands[op] of the least
         predicted slowdown among the allowed ones (device int32, -1 if none)."""
         P = self.models[op].predict(X)
         return spc.mlp_masked_argmin(P, masks.contiguous())
@@ -191,7 +195,7 @@ class Selector:
             idx = int(self.predict_indices(op, feats.view(1, NFEAT),
                                            self._mask(op, kz, dtype).view(1, -1)).item())
             if idx >= 0:
-                return tune.candidates(op)[idx], "mlp"
+                return self.cands[op][idx], "mlp"
         if A is None or B is None:
             raise ValueError("the autotune fallback needs A and B")
         return tune.best_variant(tune.autotune(plan, op, vals, A, B, kz)), "autotune"
@@ -199,6 +203,7 @@ class Selector:
     def state(self) -> dict:
         return dict(hidden=list(self.hidden), seed=self.seed,
                     models={op: m.state() for op, m in self.models.items()},
+                    cands={op: list(c) for op, c in self.cands.items()},
                     lo={op: v.tolist() for op, v in self.lo.items()},
                     hi={op: v.tolist() for op, v in self.hi.items()})
 
@@ -207,6 +212,7 @@ class Selector:
         s = cls(st["hidden"], st["seed"], device)
         for op, ms in st["models"].items():
             s.models[op] = MLP.from_state(ms, device)
+            s.cands[op] = list(st["cands"][op])
             s.lo[op] = np.array(st["lo"][op], np.float32)
             s.hi[op] = np.array(st["hi"][op], np.float32)
         return s
@@ -252,11 +258,11 @@ def collect(blocks, ks=(16, 32, 64, 128), dtypes=(spc.F32, spc.BF16), ops=tune.O
     return recs
 
 
-def dataset(recs: list, op: str):
-    """(X, T, M) arrays of the records of op."""
+def dataset(recs: list, op: str, cands=None):
+    """(X, T, M) arrays of the records of op over its candidates."""
     rs = [r for r in recs if r["op"] == op]
     X = np.stack([r["features"] for r in rs]).astype(np.float32)
-    TM = [targets(r["timings"], op) for r in rs]
+    TM = [targets(r["timings"], op, cands) for r in rs]
     return X, np.stack([t for t, _ in TM]), np.stack([m for _, m in TM])
 
 
@@ -280,10 +286,10 @@ def judge(sel: Selector, recs: list, op: str, fixed: int | None = None) -> dict:
     gain over the library default and over one fixed variant."""
     rs = [r for r in recs if r["op"] == op]
     X = torch.from_numpy(np.stack([r["features"] for r in rs]).astype(np.float32)).to(sel.device)
-    masks = torch.from_numpy(np.stack([valid_mask(op, r["kz"], r["dtype"]) for r in rs])).to(
-        sel.device)
+    cands = sel.cands[op]
+    masks = torch.from_numpy(np.stack([valid_mask(op, r["kz"], r["dtype"], cands)
+                                       for r in rs])).to(sel.device)
     idx = sel.predict_indices(op, X, masks).cpu().numpy()
-    cands = tune.candidates(op)
     reg, g_def, g_fix, r_def, r_fix, hits = [], [], [], [], [], 0
     for r, k in zip(rs, idx):
         t = r["timings"]
@@ -326,7 +332,8 @@ def save_weights(state: dict, path: str, note: str = ""):
         a = np.asarray(a, dtype="<f4")
         return dict(shape=list(a.shape), b64=base64.b64encode(a.tobytes()).decode())
 
-    out = dict(note=note, hidden=state["hidden"], seed=state["seed"], models={}, lo={}, hi={})
+    out = dict(note=note, hidden=state["hidden"], seed=state["seed"], models={}, lo={}, hi={},
+               cands=state["cands"])
     for op, m in state["models"].items():
         out["models"][op] = dict(sizes=m["sizes"], W=[enc(w) for w in m["W"]],
                                  b=[enc(b) for b in m["b"]])
@@ -346,13 +353,19 @@ def load_weights(path: str) -> dict:
 
     with open(path) as f:
         w = json.load(f)
-    st = dict(hidden=w["hidden"], seed=w["seed"], models={}, lo={}, hi={})
+    st = dict(hidden=w["hidden"], seed=w["seed"], models={}, lo={}, hi={},
+              cands=w.get("cands") or {op: _legacy_candidates(op) for op in w["models"]})
     for op, m in w["models"].items():
         st["models"][op] = dict(sizes=m["sizes"], W=[dec(x).tolist() for x in m["W"]],
                                 b=[dec(x).tolist() for x in m["b"]])
         st["lo"][op] = dec(w["lo"][op]).tolist()
         st["hi"][op] = dec(w["hi"][op]).tolist()
     return st
+
+
+def _legacy_candidates(op: str) -> list:
+    """Candidates of networks saved before the windowed SpMM family existed."""
+    return [v for v in tune.GROUP_VARIANTS if op != "sddmm" or not (v >> 8) & 1]
 
 
 def save_records(recs: list, path: str):

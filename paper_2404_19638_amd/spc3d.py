@@ -27,10 +27,14 @@ NFEAT = 23
 FEATURES_BUFFER_BYTES = 256
 
 
-def variant(lg_lanes: int, lg_items: int, wide: int = 0) -> int:
+VARIANT_WINDOW = 0x200
+
+
+def variant(lg_lanes: int, lg_items: int, wide: int = 0, window: int = 0) -> int:
     """SPC3D_VARIANT: 2^lg_lanes lanes per nonzero, 64 * 2^lg_items slots per work item;
-    wide=1 gathers up to 16 rows per batch in SpMM (8 otherwise)."""
-    return lg_lanes | (lg_items << 4) | (wide << 8)
+    wide=1 gathers up to 16 rows per batch in SpMM (8 otherwise); window=1 picks the
+    windowed SpMM family (SPC3D_VARIANT_WINDOW)."""
+    return lg_lanes | (lg_items << 4) | (wide << 8) | (VARIANT_WINDOW if window else 0)
 
 
 class Spc3dError(RuntimeError):

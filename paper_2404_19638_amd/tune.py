@@ -14,15 +14,18 @@ from . import spc3d as spc
 
 LG_LANES = (1, 2, 3, 4, 5, 6)
 LG_ITEMS = (0, 1, 2, 3, 4)
-ALL_VARIANTS = [spc.variant(a, b, w) for w in (0, 1) for a in LG_LANES for b in LG_ITEMS]
+# group-run SpMM family (8- or 16-row batches), then the windowed family
+GROUP_VARIANTS = [spc.variant(a, b, w) for w in (0, 1) for a in LG_LANES for b in LG_ITEMS]
+WINDOW_VARIANTS = [spc.variant(a, b, 0, 1) for a in (1, 2, 3) for b in LG_ITEMS]
+ALL_VARIANTS = GROUP_VARIANTS + WINDOW_VARIANTS
 OPS = ("sddmm", "spmm", "sddmm_spmm")
 OPCODE = {"sddmm": spc.OP_SDDMM, "spmm": spc.OP_SPMM, "sddmm_spmm": spc.OP_SDDMM_SPMM}
 
 
 def candidates(op: str) -> list:
-    """Variants that differ for op: the SDDMM kernel has no wide batches."""
+    """Variants that differ for op: the SDDMM kernel ignores the SpMM bits."""
     if op == "sddmm":
-        return [v for v in ALL_VARIANTS if not (v >> 8) & 1]
+        return [v for v in ALL_VARIANTS if not (v >> 8) & 3]
     return list(ALL_VARIANTS)
 
 

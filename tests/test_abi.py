@@ -59,3 +59,39 @@ def test_host_validation(lib):
     lib.spc3d_status_string.restype = ctypes.c_char_p
     assert lib.spc3d_status_string(3) == b"workspace or buffer too small"
     assert lib.spc3d_version() >= 100
+
+
+def test_variant_check_rules(lib):
+    """spc3d_variant_check is host-only: the shape rules without a launch."""
+    f = lib.spc3d_variant_check
+    f.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int, ctypes.c_int]
+    SDDMM, SPMM, FUSED = 0, 1, 2
+    F32, BF16 = 0, 1
+    OK, INVALID, UNSUPPORTED = 0, 1, 4
+
+    def var(lanes, items, wide=0, window=0):
+        return lanes | (items << 4) | (wide << 8) | (0x200 if window else 0)
+
+    for op in (SDDMM, SPMM, FUSED):
+        assert f(op, 32, F32, -1) == OK and f(op, 128, BF16, -1) == OK
+        assert f(op, 32, F32, 0) == INVALID            # 1 lane per entry is not a shape
+        assert f(op, 32, F32, var(7, 0)) == INVALID
+        assert f(op, 32, F32, var(3, 5)) == INVALID     # items beyond 1024 slots
+        assert f(op, 32, F32, var(3, 0, 1, 1)) == INVALID   # wide and window together
+        assert f(op, 32, F32, 0x400 | 3) == INVALID
+        assert f(op, 0, F32, -1) == INVALID and f(op, 32, 7, -1) == INVALID
+    assert f(3, 32, F32, -1) == INVALID
+    # kz = 128 FP32 is 32 vectors: 2 lanes would need 16 per lane
+    assert f(SDDMM, 128, F32, var(1, 0)) == UNSUPPORTED
+    assert f(SDDMM, 128, F32, var(3, 0)) == OK
+    # group-run SpMM needs >= 8 slots per group (16 with wide batches)
+    assert f(SPMM, 32, F32, var(3, 0)) == OK            # 64 slots / 8 groups
+    assert f(SPMM, 32, F32, var(2, 0)) == UNSUPPORTED   # 64 / 16 groups = 4
+    assert f(SPMM, 32, F32, var(3, 0, 1)) == UNSUPPORTED
+    assert f(SPMM, 32, F32, var(3, 1, 1)) == OK
+    # the windowed family has no run-length rule but takes 2, 4 or 8 lanes
+    assert f(SPMM, 32, F32, var(2, 0, 0, 1)) == OK
+    assert f(FUSED, 32, F32, var(3, 4, 0, 1)) == OK
+    assert f(SPMM, 32, F32, var(4, 0, 0, 1)) == UNSUPPORTED
+    # SDDMM ignores the SpMM bits
+    assert f(SDDMM, 32, F32, var(4, 0, 0, 1)) == OK

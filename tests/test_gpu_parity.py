@@ -174,7 +174,11 @@ def _local_inputs(p, ref, k0, kz, dtype=np.float32):
     return Aloc, Bloc
 
 
-VARIANTS = [-1, (1, 2), (2, 1), (3, 0), (3, 2), (3, 4), (4, 2), (5, 3), (6, 4), (3, 3, 1), (1, 2, 1)]
+VARIANTS = [-1, (1, 2), (2, 1), (3, 0), (3, 2), (3, 4), (4, 2), (5, 3), (6, 4), (3, 3, 1), (1, 2, 1),
+            # windowed SpMM family
+            (1, 0, 0, 1), (2, 0, 0, 1), (3, 0, 0, 1), (2, 3, 0, 1), (3, 3, 0, 1), (1, 4, 0, 1),
+            (5, 2, 0, 1), (6, 4, 0, 1)]
+WINDOW_VARIANTS = [v for v in VARIANTS if isinstance(v, tuple) and len(v) == 4]
 
 
 def _variant(spc, v):
@@ -221,6 +225,75 @@ def test_sddmm_spmm_parity(name, kz):
         fo, fy = spc.sddmm_spmm(plan, vals_slot, A, B, kz, variant=vv)
         assert_within_mag(_np(fo), o_sd, m_sd, what=f"fused sddmm v={v}")
         assert_within_mag(_np(fy), o_sp, m_sp, what=f"fused spmm v={v}")
+
+
+def _row_pattern(lengths, ncols, seed):
+    """COO entries of rows with the given lengths (row i has lengths[i] distinct columns)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for r, L in enumerate(lengths):
+        rows.append(np.full(L, r, np.int64))
+        cols.append(np.sort(rng.choice(ncols, size=L, replace=False)).astype(np.int64))
+    return np.concatenate(rows), np.concatenate(cols)
+
+
+SEGMENT_CASES = {
+    # one hub row over many work items, between short rows
+    "hub": [1, 2, 3000, 1, 5],
+    # every row a single entry (a row ends at every slot)
+    "singletons": [1] * 777,
+    # rows of exactly one window, and rows that end one slot past a window
+    "window_aligned": [64] * 9 + [65, 63, 1, 64],
+    # one entry only
+    "one": [1],
+    # rows ending exactly at group ends for 2, 4 and 8 lanes, then a ragged tail
+    "group_aligned": [2, 2, 4, 4, 8, 8, 16, 1, 3, 5, 7, 9, 11, 13, 130, 2],
+}
+
+
+@pytest.mark.parametrize("case", sorted(SEGMENT_CASES))
+def test_spmm_row_segments(case):
+    """Row boundaries at every position relative to groups, windows and work
+    items: every SpMM family and the fused pass against the oracle."""
+    spc = _spc()
+    lengths = SEGMENT_CASES[case]
+    ncols = max(4000, max(lengths))
+    rows, cols = _row_pattern(lengths, ncols, 17)
+    kz = 32
+    R, C = len(lengths), ncols
+    vals = synth.uniform_f32(5, rows.shape[0])
+    A_src = synth.dense_f32(6, 0, R, kz)
+    B_src = synth.dense_f32(7, 0, C, kz)
+    ref = oracle.relabel(rows, cols, (0, R), (0, C))
+    Aloc, Bloc = _local_inputs_raw(ref, (0, R), (0, C), A_src, B_src, kz)
+    o_sd, m_sd = oracle.sddmm(rows, cols, 0, 0, vals, A_src, B_src, 0, kz)
+    o_sd, m_sd = o_sd[ref["perm"]], m_sd[ref["perm"]]
+    o_sp, m_sp = oracle.spmm(rows, cols, 0, 0, ref["lmap_r"], ref["R"], vals, B_src, 0, kz)
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               (0, R), (0, C))
+    vs = torch.from_numpy(vals[ref["perm"]]).to(DEV)
+    A = torch.from_numpy(Aloc).to(DEV)
+    B = torch.from_numpy(Bloc).to(DEV)
+    for v in [-1, (3, 0), (2, 3), (3, 3, 1)] + WINDOW_VARIANTS:
+        vv = _variant(spc, v)
+        _say(f"segments {case} variant={v}")
+        try:
+            Y = spc.spmm(plan, vs, B, 0, kz, variant=vv)
+        except spc.Spc3dError as e:
+            assert e.status == spc.ERR_UNSUPPORTED, e
+            continue
+        assert_within_mag(_np(Y), o_sp, m_sp, what=f"spmm {case} v={v}")
+        Y2 = spc.spmm(plan, vs, B, 0, kz, variant=vv, out=Y.clone(), mode=spc.ACCUMULATE)
+        assert_within_mag(_np(Y2), 2 * o_sp, 2 * m_sp, what=f"spmm acc {case} v={v}")
+        fo, fy = spc.sddmm_spmm(plan, vs, A, B, kz, variant=vv)
+        assert_within_mag(_np(fo), o_sd, m_sd, what=f"fused sddmm {case} v={v}")
+        assert_within_mag(_np(fy), o_sp, m_sp, what=f"fused spmm {case} v={v}")
+        assert torch.equal(spc.spmm(plan, vs, B, 0, kz, variant=vv), Y), "not deterministic"
+
+
+def _local_inputs_raw(ref, rr, cr, A_src, B_src, kz):
+    return (oracle.gather_f32(ref["gmap_r"], rr[0], A_src, 0, kz),
+            oracle.gather_f32(ref["gmap_c"], cr[0], B_src, 0, kz))
 
 
 def test_pattern_only_and_accumulate_modes():
