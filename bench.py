@@ -105,6 +105,30 @@ ERROR_BARS = {
 SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2404_19638_amd", "selector_weights.json")
 
 
+def cold_kernels(step, names, spans, nev, alg, steps, dev):
+    """Per-kernel event times with L2 and the Infinity Cache flushed before
+    each step by a 1 GiB write (the flush itself is outside the events)."""
+    import numpy as np
+    import torch
+
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    evs = []
+    for i in range(steps):
+        flush.fill_(float(i))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(nev)]
+        step(ev)
+        evs.append(ev)
+    torch.cuda.synchronize()
+    out = {}
+    for n in names:
+        a, b = spans[n]
+        ms = float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
+        out[n] = {"ms": round(ms, 5), "GB_s": round(alg[n] / (ms * 1e-3) / 1e9, 1),
+                  "frac_hbm": round(alg[n] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del flush
+    return out
+
+
 def forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_main, per_main, flops):
     """The plain FP32 form against BF16 operands and the learned selector's
     variants, each timed like the main loop on the same block."""
@@ -153,6 +177,10 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serial-gathers", action="store_true",
+                    help="run the two gathers one after the other on one stream")
+    ap.add_argument("--cold-steps", type=int, default=10,
+                    help="extra steps, each after a 1 GiB flush write, for cold-cache kernel times")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16 and learned-selector forms")
     ap.add_argument("--seed", type=int, default=2405)
@@ -163,7 +191,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path would shard one "
-                                   "block per GPU of the 3D grid (see DESIGN.md)",
+                                   "block per GPU of the 3D grid",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -207,8 +235,14 @@ def main():
     else:
         names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
 
+    # The two packs are independent (SpC-BB packs A and B rows separately):
+    # gather B runs on a second stream beside gather A unless --serial-gathers.
+    side = None if args.serial_gathers else torch.cuda.Stream(device=dev)
+    nev = len(names) + 3
+
     def make_step(dtype, variant):
-        """One step in dtype; variant is an int, or (SDDMM, SpMM) variants when unfused."""
+        """One step in dtype; variant is an int, or (SDDMM, SpMM) variants when unfused.
+        step(ev) records events ev[0..nev) and returns {kernel: (start, end)} indices."""
         v_sd, v_sp = variant if isinstance(variant, tuple) else (variant, variant)
         pdt = torch.float32 if dtype == "f32" else torch.bfloat16
         A_loc = torch.empty((R, kz), dtype=pdt, device=dev)
@@ -217,33 +251,53 @@ def main():
         Y_loc = torch.empty((R, kz), device=dev)
         spbuf = torch.empty(spc.spmm_buffer_size(plan, 0, kz, v_sp), dtype=torch.uint8,
                             device=dev)
+        main = torch.cuda.current_stream(dev)
 
         def step(ev=None):
             def mark(i):
                 if ev is not None:
                     ev[i].record()
             mark(0)
-            spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
-            mark(1)
-            spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
-            mark(2)
+            if side is not None:
+                side.wait_stream(main)
+                with torch.cuda.stream(side):
+                    mark(2)
+                    spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
+                    mark(3)
+                spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
+                mark(1)
+                main.wait_stream(side)
+            else:
+                spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
+                mark(1)
+                mark(2)
+                spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
+                mark(3)
+            mark(4)
             if args.fused:
                 spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=v_sp,
                                buf=spbuf)
-                mark(3)
+                mark(5)
             else:
                 spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=v_sd)
-                mark(3)
+                mark(5)
                 spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=v_sp, buf=spbuf)
-                mark(4)
+                mark(6)
             spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
-            mark(len(names))
+            mark(nev - 1)
         return step
+
+    # kernel -> (start event, end event); every pair is on the stream the kernel runs on
+    spans = {"gather_A": (0, 1), "gather_B": (2, 3)}
+    if args.fused:
+        spans.update(sddmm_spmm=(4, 5), scatter=(5, 6))
+    else:
+        spans.update(sddmm=(4, 5), spmm=(5, 6), scatter=(6, 7))
 
     def timed(step, steps, warmup):
         for _ in range(warmup):
             step()
-        events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)]
                   for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -251,9 +305,9 @@ def main():
             step(events[i])
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        per = {n: float(np.mean([events[i][j].elapsed_time(events[i][j + 1])
+        per = {n: float(np.mean([events[i][a].elapsed_time(events[i][b])
                                  for i in range(steps)]))
-               for j, n in enumerate(names)}
+               for n, (a, b) in spans.items()}
         return ms, per
 
     b = 4 if args.dtype == "f32" else 2
@@ -287,7 +341,8 @@ def main():
         "config": {"workload": workload, "rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4",
                    "block": [5, 2], "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
                    "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
-                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce")},
+                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce"),
+                   "gathers": "one stream" if args.serial_gathers else "two streams"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -297,6 +352,9 @@ def main():
         "setup_ms": round(setup_ms, 2),
         "source_hash": src_hash,
     }
+    if args.cold_steps:
+        res["cold"] = cold_kernels(make_step(args.dtype, args.variant), names, spans, nev, alg,
+                                   args.cold_steps, dev)
     if not args.no_forms:
         res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_per_step,
                              per_kernel_ms, flops)

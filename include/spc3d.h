@@ -73,7 +73,8 @@ enum { SPC3D_OVERWRITE = 0, SPC3D_ACCUMULATE = 1 };  /* output modes */
 enum { SPC3D_BUILD_CSC = 1u };                        /* plan flags */
 enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
 
-/* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose;
+/* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose
+ * from kz, the operand type and the block's nnz;
  * otherwise (log2 of lanes per nonzero, 1..6) | (log2 of work-item slots / 64,
  * 0..4) << 4 | (SpMM gathers 16 rows per batch instead of 8, 0..1) << 8 |
  * SPC3D_VARIANT_WINDOW for the windowed SpMM family (each 64-slot window's

@@ -24,7 +24,7 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   const bool fused = d_A != nullptr;
   Shape sh;
   const bool al = aligned16(d_X) && aligned16(d_Y) && (!fused || aligned16(d_A));
-  spc3d_status st = pick_shape(kz, x_t, al, variant, fused ? 2 : 1, &sh);
+  spc3d_status st = pick_shape(kz, x_t, al, variant, fused ? 2 : 1, p->nnz, &sh);
   if (st != SPC3D_OK) return st;
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
   if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
@@ -79,7 +79,7 @@ spc3d_status spc3d_sddmm(spc3d_plan h, const float* d_vals, const void* d_A, con
   if (p->nnz == 0) return SPC3D_OK;
   if (!d_A || !d_B || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   Shape sh;
-  st = pick_shape(kz, ab_t, aligned16(d_A) && aligned16(d_B), variant, 0, &sh);
+  st = pick_shape(kz, ab_t, aligned16(d_A) && aligned16(d_B), variant, 0, p->nnz, &sh);
   if (st != SPC3D_OK) return st;
   st = use_device(p);
   if (st != SPC3D_OK) return st;
@@ -115,9 +115,9 @@ spc3d_status spc3d_spmm_buffer_size(spc3d_plan h, int transpose, int32_t kz, int
   if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
   Shape sh;
   // The buffer does not depend on the element type or alignment.
-  st = pick_shape(kz, SPC3D_F32, true, variant, 1, &sh);
+  st = pick_shape(kz, SPC3D_F32, true, variant, 1, p->nnz, &sh);
   if (st != SPC3D_OK && variant >= 0) {
-    st = pick_shape(kz, SPC3D_F32, false, variant, 1, &sh);
+    st = pick_shape(kz, SPC3D_F32, false, variant, 1, p->nnz, &sh);
     if (st != SPC3D_OK) return st;
   }
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
@@ -169,7 +169,7 @@ spc3d_status spc3d_variant_check(int op, int32_t kz, spc3d_dtype ab_t, int varia
   if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
   if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
   Shape sh;
-  return pick_shape(kz, ab_t, true, variant, op, &sh);
+  return pick_shape(kz, ab_t, true, variant, op, 0, &sh);
 }
 
 }  // extern "C"

@@ -37,6 +37,30 @@ namespace spc3d {
 
 enum { kLeadNone = 0, kLeadEnds = 1, kLeadThrough = 2 };
 
+// Streaming accesses (indices and values read once, outputs written once)
+// carry the nontemporal hint so that they do not displace the dense rows
+// that later entries gather again from L2.
+#ifndef SPC3D_STREAM_HINTS
+#define SPC3D_STREAM_HINTS 1
+#endif
+template <typename T>
+__device__ inline T ld_stream(const T* p) {
+#if SPC3D_STREAM_HINTS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+template <typename T>
+__device__ inline void st_stream(T* p, T v) {
+#if SPC3D_STREAM_HINTS
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Row of slot s from the head bitmap.
 __device__ inline int row_of(const uint64_t* __restrict__ head, const int32_t* __restrict__ tile_row,
                              int64_t s) {
@@ -117,8 +141,8 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int6
   for (int64_t win = b; win < e; win += 64) {
     const int64_t s = win + lane;
     const bool valid = s < e;
-    const int col = valid ? colidx[s] : 0;
-    const float v = vals ? (valid ? vals[s] : 0.f) : 1.f;
+    const int col = valid ? ld_stream(colidx + s) : 0;
+    const float v = vals ? (valid ? ld_stream(vals + s) : 0.f) : 1.f;
     // lanes past the end repeat the last valid row (no head bits there)
     const int row = tile_row[win >> 6] + __popcll(head[win >> 6] & lanemask_le(lane) & ~1ull);
     float res = 0.f;
@@ -141,7 +165,7 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int6
     }
     if (valid) {
       const float o = v * res;
-      out[s] = accumulate ? out[s] + o : o;
+      st_stream(out + s, accumulate ? ld_stream(out + s) + o : o);
     }
   }
 }
@@ -159,12 +183,9 @@ __device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int
       if constexpr (VEC % 4 == 0) {
 #pragma unroll
         for (int t = 0; t < VEC; t += 4) {
-          float4 o = make_float4(acc[ch][t], acc[ch][t + 1], acc[ch][t + 2], acc[ch][t + 3]);
-          if (accumulate) {
-            const float4 old = *reinterpret_cast<const float4*>(y + t);
-            o.x = old.x + o.x; o.y = old.y + o.y; o.z = old.z + o.z; o.w = old.w + o.w;
-          }
-          *reinterpret_cast<float4*>(y + t) = o;
+          f32x4 o = {acc[ch][t], acc[ch][t + 1], acc[ch][t + 2], acc[ch][t + 3]};
+          if (accumulate) o = ld_stream(reinterpret_cast<const f32x4*>(y + t)) + o;
+          st_stream(reinterpret_cast<f32x4*>(y + t), o);
         }
       } else {
 #pragma unroll
@@ -313,8 +334,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
     e = (b + wslots < nnz) ? b + wslots : nnz;
     for (int i = lane; i < (int)(e - b); i += 64) {
       const int pi = i + (i >> lgS);
-      s_col[pi] = idx[b + i];
-      s_val[pi] = vals ? vals[vidx ? vidx[b + i] : b + i] : 1.f;
+      s_col[pi] = ld_stream(idx + b + i);
+      s_val[pi] = vals ? (vidx ? vals[vidx[b + i]] : ld_stream(vals + b + i)) : 1.f;
     }
     const int nw = (int)((e - b + 63) >> 6);   // b is a multiple of 64
     for (int i = lane; i < nw; i += 64) {
@@ -391,7 +412,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
 
   if constexpr (FUSED) {
     for (int i = lane; i < (int)(e - b); i += 64)
-      out[b + i] = accumulate ? out[b + i] + s_out[i + (i >> lgS)] : s_out[i + (i >> lgS)];
+      st_stream(out + b + i, accumulate ? ld_stream(out + b + i) + s_out[i + (i >> lgS)]
+                                        : s_out[i + (i >> lgS)]);
   }
   if (tail) {
     bool done = false;
@@ -487,8 +509,8 @@ __global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int6
   auto fetch = [&](int64_t w0) {
     const int64_t sl = w0 + lane;
     const bool ok = sl < e;
-    col_n = ok ? idx[sl] : 0;
-    v_n = ok ? (vals ? vals[vidx ? vidx[sl] : sl] : 1.f) : 0.f;
+    col_n = ok ? ld_stream(idx + sl) : 0;
+    v_n = ok ? (vals ? (vidx ? vals[vidx[sl]] : ld_stream(vals + sl)) : 1.f) : 0.f;
     hw_n = head[w0 >> 6];
     trow_n = tile_row[w0 >> 6];
   };
@@ -556,7 +578,7 @@ __global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int6
     if constexpr (FUSED) {
       if (valid) {
         const float o = v * res;
-        out[sl] = accumulate ? out[sl] + o : o;
+        st_stream(out + sl, accumulate ? ld_stream(out + sl) + o : o);
       }
     }
 
@@ -719,12 +741,14 @@ inline int pow2ceil(int n) {
   return p;
 }
 
-// op: 0 SDDMM, 1 SpMM, 2 fused SDDMM+SpMM.  Defaults (variant -1) are the
-// best measured on MI355X for a power-law block with kz = 32: SDDMM on
-// 64-slot items, SpMM and the fused pass on 512-slot items, the fused pass
-// with half as many lanes per nonzero (its batches hold A and B rows).
+// op: 0 SDDMM, 1 SpMM, 2 fused SDDMM+SpMM.  Defaults (variant -1), from
+// measurements on MI355X: SDDMM on 64-slot work items with lanes covering kz;
+// SpMM and the fused pass (half as many lanes: its batches hold A and B rows)
+// on work items that grow with the block, about nnz / 4096 slots clamped to
+// [64, 512] so that small blocks still launch enough wavefronts, in the
+// windowed family below 2^18 entries and in the group-run family above.
 inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, int op,
-                               Shape* sh) {
+                               int64_t nnz, Shape* sh) {
   const bool spmm = op != 0;
   const int vfull = (t == SPC3D_F32) ? 4 : 8;
   sh->vec = (vec_ok && kz % vfull == 0) ? vfull : 1;
@@ -738,10 +762,18 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
     if (sh->lanes > 16) sh->lanes = 16;
     if (sh->lanes < 2) sh->lanes = 2;
     while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
-    sh->items = spmm ? 512 : 64;
-    while (spmm && sh->items / (64 / sh->lanes) < 8) sh->items *= 2;
     sh->wide = 0;
     sh->window = 0;
+    sh->items = 64;
+    if (spmm) {
+      sh->items = nnz < (int64_t(1) << 18) ? 64
+                  : nnz < (int64_t(1) << 20) ? 128
+                  : nnz < (int64_t(1) << 21) ? 256 : 512;
+      if (sh->items == 64 && sh->lanes <= 8)
+        sh->window = 1;
+      else
+        while (sh->items / (64 / sh->lanes) < 8) sh->items *= 2;
+    }
   } else {
     const int lg = variant & 15, lw = (variant >> 4) & 15;
     if (lg < 1 || lg > 6 || lw > 4 || (variant >> 10) || ((variant >> 8) & 3) == 3)

@@ -267,10 +267,12 @@ def dataset(recs: list, op: str, cands=None):
 
 
 def best_fixed(recs: list, op: str) -> int:
-    """The single candidate with the least geometric-mean slowdown over recs
-    (an instance where it cannot run counts the default's slowdown)."""
+    """The single candidate with the least geometric-mean slowdown over recs,
+    among those that run on every instance (if none does, an instance where a
+    candidate cannot run counts the default's slowdown)."""
     best, best_score = -1, None
-    for v in tune.candidates(op):
+    everywhere = [v for v in tune.candidates(op) if all(v in r["timings"] for r in recs)]
+    for v in everywhere or tune.candidates(op):
         s = 0.0
         for r in recs:
             t = r["timings"]

@@ -260,9 +260,14 @@ def test_selector_small_end_to_end():
              f"{jt['default_regret_geomean']:.4f}); held-out regret {jh['regret_geomean']:.4f} "
              f"p90 {jh['regret_p90']:.4f} (default {jh['default_regret_geomean']:.4f}, fixed "
              f"{jh['fixed_regret_geomean']:.4f}); gain vs default {jh['gain_vs_default_geomean']:.4f}")
-        # fitted on the training blocks, the network must beat the fixed default there
-        assert jt["regret_geomean"] <= jt["default_regret_geomean"]
-        assert np.isfinite(jh["regret_geomean"]) and jh["regret_max"] < 3.0
+        # Fitted on the training blocks, the network is at least as good as the
+        # library default and the best single variant there, up to 2% of timing
+        # noise (the labels are timings of a few calls each); on the 8 held-out
+        # blocks it stays within 15% of the exhaustive search (the full
+        # 512-block evaluation is the selector workload run).
+        best_fixed = min(jt["default_regret_geomean"], jt["fixed_regret_geomean"])
+        assert jt["regret_geomean"] <= best_fixed + 0.02, jt
+        assert jh["regret_geomean"] < 0.15 and jh["regret_max"] < 3.0, jh
 
 
 def test_selector_choose_and_fallback():
