@@ -177,8 +177,6 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32")
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serial-gathers", action="store_true",
-                    help="run the two gathers one after the other on one stream")
     ap.add_argument("--cold-steps", type=int, default=10,
                     help="extra steps, each after a 1 GiB flush write, for cold-cache kernel times")
     ap.add_argument("--no-forms", action="store_true",
@@ -235,9 +233,10 @@ def main():
     else:
         names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
 
-    # The two packs are independent (SpC-BB packs A and B rows separately):
-    # gather B runs on a second stream beside gather A unless --serial-gathers.
-    side = None if args.serial_gathers else torch.cuda.Stream(device=dev)
+    # Events: 0 start, 1 after gather A, 2 / 3 around gather B, 4 start of the
+    # compute, then one after each remaining kernel.  (Running the two packs on
+    # two streams was measured slower than one after the other: they contend
+    # for the same HBM bandwidth.)
     nev = len(names) + 3
 
     def make_step(dtype, variant):
@@ -251,28 +250,17 @@ def main():
         Y_loc = torch.empty((R, kz), device=dev)
         spbuf = torch.empty(spc.spmm_buffer_size(plan, 0, kz, v_sp), dtype=torch.uint8,
                             device=dev)
-        main = torch.cuda.current_stream(dev)
 
         def step(ev=None):
             def mark(i):
                 if ev is not None:
                     ev[i].record()
             mark(0)
-            if side is not None:
-                side.wait_stream(main)
-                with torch.cuda.stream(side):
-                    mark(2)
-                    spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
-                    mark(3)
-                spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
-                mark(1)
-                main.wait_stream(side)
-            else:
-                spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
-                mark(1)
-                mark(2)
-                spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
-                mark(3)
+            spc.gather(plan, spc.ROWS, A_src, k0, kz, out=A_loc)
+            mark(1)
+            mark(2)
+            spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
+            mark(3)
             mark(4)
             if args.fused:
                 spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=v_sp,
@@ -341,8 +329,7 @@ def main():
         "config": {"workload": workload, "rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4",
                    "block": [5, 2], "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
                    "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
-                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce"),
-                   "gathers": "one stream" if args.serial_gathers else "two streams"},
+                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce")},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

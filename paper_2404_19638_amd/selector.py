@@ -267,9 +267,10 @@ def dataset(recs: list, op: str, cands=None):
 
 
 def best_fixed(recs: list, op: str) -> int:
-    """The single candidate with the least geometric-mean slowdown over recs,
-    among those that run on every instance (if none does, an instance where a
+    """The single candidate with the least geometric-mean slowdown over the
+    records of op, among those that run on every instance (if none does, an instance where a
     candidate cannot run counts the default's slowdown)."""
+    recs = [r for r in recs if r["op"] == op]
     best, best_score = -1, None
     everywhere = [v for v in tune.candidates(op) if all(v in r["timings"] for r in recs)]
     for v in everywhere or tune.candidates(op):
