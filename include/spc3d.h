@@ -226,6 +226,41 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan plan, const float* d_alpha, const 
                                    float* d_de, void* d_buf, size_t buf_bytes,
                                    hipStream_t stream);
 
+/* alpha[p] = exp(e[p] - stats[2r]) / stats[2r+1] for every entry p of local
+ * row r: the softmax weights rebuilt from scores and the per-row (max, sum of
+ * exp(e - max)) that spc3d_attention_fwd stores.  d_stats holds 2R floats
+ * (8-byte aligned); d_e and d_alpha hold nnz values and may alias. */
+spc3d_status spc3d_row_softmax_apply(spc3d_plan plan, const float* d_e, const float* d_stats,
+                                     float* d_alpha, hipStream_t stream);
+
+/* Bytes of scratch spc3d_attention_fwd needs for (kz, dtype, variant). */
+spc3d_status spc3d_attention_fwd_buffer_size(spc3d_plan plan, int32_t kz, spc3d_dtype t,
+                                             int variant, size_t* bytes);
+
+/* Fused masked attention forward over the block's pattern (the SDDMM ->
+ * softmax -> SpMM chain of a graph-attention layer in one pass; an extension
+ * built on Eq. (1) and Eq. (2)):
+ *   e_p = sum_k Q[r*kz + k] * K[c*kz + k]               (entry p = (r, c))
+ *   out[r*kz + k] = sum_{p in row r} exp(e_p - m_r) / s_r * V[c*kz + k]
+ * with m_r = max of row r's scores and s_r = sum_{p in row r} exp(e_p - m_r);
+ * d_stats (2R floats, 8-byte aligned, may be NULL) receives (m_r, s_r).
+ * Q is [R x kz], K and V are [C x kz], packed row-major, 16-byte aligned, of
+ * type t (FP32 or bfloat16); out is [R x kz] FP32.  Scores never reach
+ * memory; each row's partial (max, sum, weighted sum) triples are merged by
+ * rescaling to the larger maximum in an order fixed by the pattern, so the
+ * result is deterministic.  kz*sizeof(t) must be 64, 128, 256 or 512 bytes
+ * (FP32 kz 16, 32, 64, 128; bfloat16 kz 32, 64, 128, 256), else
+ * SPC3D_ERR_UNSUPPORTED (sddmm, row_softmax and spmm compute the same).
+ * Scores of -inf: a row whose scores are all -inf gives the mean of its V
+ * rows rather than NaN.
+ * variant: -1, or lg2(lanes per entry) (2..4) | lg2(slots per lane group)
+ * << 4 (4..6).  d_buf (256-byte aligned) holds at least
+ * spc3d_attention_fwd_buffer_size bytes.  Asynchronous on stream. */
+spc3d_status spc3d_attention_fwd(spc3d_plan plan, const void* d_Q, const void* d_K,
+                                 const void* d_V, spc3d_dtype t, int32_t kz, float* d_out,
+                                 float* d_stats, int variant, void* d_buf, size_t buf_bytes,
+                                 hipStream_t stream);
+
 /* Per-entry product out[p] = a[p] * b[p] for the nnz entries of a plan (slot
  * order).  The backward of SDDMM scales the upstream gradient by the sampling
  * values with it: d(s_p <a_i,b_j>)/d a_i = s_p b_j.  Any of the arrays may

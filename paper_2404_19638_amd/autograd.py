@@ -128,6 +128,40 @@ class ScatterReduceFn(torch.autograd.Function):
         return None, None, dpacked, dout, None
 
 
+class FusedAttentionFn(torch.autograd.Function):
+    """out = rowsoftmax(SDDMM(pattern, Q, Kf)) . V in one fused pass
+    (spc3d_attention_fwd).  The backward recomputes the scores with one SDDMM,
+    rebuilds alpha from the stored row (max, sum) pairs, and then runs the
+    chain of the unfused layer: dalpha = SDDMM(dout, V), de = softmax
+    backward, dQ = SpMM(de, Kf), dKf = SpMM^T(de, Q), dV = SpMM^T(alpha, dout)."""
+
+    @staticmethod
+    def forward(ctx, plan, Q, Kf, V):
+        Q, Kf, V = Q.contiguous(), Kf.contiguous(), V.contiguous()
+        out, stats = spc.attention_fwd(plan, Q, Kf, V)
+        ctx.plan = plan
+        ctx.save_for_backward(Q, Kf, V, stats)
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        plan = ctx.plan
+        Q, Kf, V, stats = ctx.saved_tensors
+        dout = dout.contiguous()
+        e = spc.sddmm(plan, None, Q, Kf)
+        alpha = spc.row_softmax_apply(plan, e, stats, out=e)
+        dalpha = spc.sddmm(plan, None, dout, V)
+        de = spc.row_softmax_bwd(plan, alpha, dalpha, out=dalpha)
+        dQ = dK = dV = None
+        if _needs(ctx, 1):
+            dQ = spc.spmm(plan, de, Kf, transpose=0)
+        if _needs(ctx, 2):
+            dK = spc.spmm(plan, de, Q, transpose=1)
+        if _needs(ctx, 3):
+            dV = spc.spmm(plan, alpha, dout, transpose=1)
+        return None, dQ, dK, dV
+
+
 def sddmm(plan, vals, A, B):
     return SDDMMFn.apply(plan, vals, A, B)
 
@@ -148,12 +182,27 @@ def scatter_reduce(plan, axis, packed, dst, k0):
     return ScatterReduceFn.apply(plan, axis, packed, dst, k0)
 
 
-def gnn_attention(plan, Q, Kf, V):
+def _need_fused(Q, Kf, V):
+    if not spc.attention_supported(Q.shape[1], spc.F32):
+        raise ValueError(f"the fused attention pass does not cover K={Q.shape[1]}")
+    if not all(t.data_ptr() % 16 == 0 for t in (Q, Kf, V)):
+        raise ValueError("the fused attention pass needs 16-byte aligned Q, Kf and V")
+
+
+def gnn_attention(plan, Q, Kf, V, fused: bool = False):
     """Masked attention over the block's pattern: SDDMM edge scores (s == 1),
     row softmax over each row's stored entries, SpMM aggregation of V.
 
     Q is [R, K] (local rows), Kf and V are [C, K] (local columns); returns [R, K].
+    fused=True runs the forward as one pass (spc3d_attention_fwd; K must be
+    covered by it, see spc.attention_supported) and recomputes the scores in
+    the backward.  The default is the three separate kernels: on MI355X the
+    layer is bound by the gathers of Kf and V rows, which the fused pass keeps
+    live together, and it measured no faster in FP32 beyond 2^16 vertices.
     """
+    if fused:
+        _need_fused(Q, Kf, V)
+        return FusedAttentionFn.apply(plan, Q, Kf, V)
     e = sddmm(plan, None, Q, Kf)
     alpha = row_softmax(plan, e)
     return spmm(plan, alpha, V, 0)

@@ -39,6 +39,14 @@ struct SoftmaxStat {
     return {m, a.s * expf(a.m - m) + b.s * expf(b.m - m)};
   }
   static __device__ inline float input(const float* x0, const float*, int64_t p) { return x0[p]; }
+  template <int N>
+  static __device__ inline void loadv(const float* x0, const float*, int64_t p, float (&x)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      const float4 v = *reinterpret_cast<const float4*>(x0 + p + i);
+      x[i] = v.x; x[i + 1] = v.y; x[i + 2] = v.z; x[i + 3] = v.w;
+    }
+  }
 };
 
 struct DotSum {
@@ -51,9 +59,16 @@ struct DotSum {
   static __device__ inline float input(const float* x0, const float* x1, int64_t p) {
     return x0[p] * x1[p];
   }
+  template <int N>
+  static __device__ inline void loadv(const float* x0, const float* x1, int64_t p, float (&x)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(x0 + p + i);
+      const float4 b = *reinterpret_cast<const float4*>(x1 + p + i);
+      x[i] = a.x * b.x; x[i + 1] = a.y * b.y; x[i + 2] = a.z * b.z; x[i + 3] = a.w * b.w;
+    }
+  }
 };
-
-enum { kNone = 0, kEnds = 1, kThrough = 2 };
 
 __device__ inline int row_of_slot(const uint64_t* __restrict__ head,
                                   const int32_t* __restrict__ tile_row, int64_t s) {
@@ -65,7 +80,25 @@ __device__ inline bool head_at(const uint64_t* __restrict__ head, int64_t s) {
 }
 
 // stats[r] = reduction of row r for rows inside one item; carries for the rest.
+// Each lane owns a run of kRun consecutive slots; the run's head word, its
+// inputs (one 16-byte load per input array where aligned) and the head bit
+// after the item are loaded before any is used.  Rows that start and end in
+// a run are written directly; the part of a row before a run's first row
+// start ("lead") and the part after its last ("tail") meet in a segmented
+// suffix scan over the 64 lanes (shuffles, 6 steps, a fixed order): lane l's
+// tail row continues through the leads of lanes l+1, l+2, ... up to the first
+// lane in which a row starts.
+constexpr int kRun = 8;
+
 template <class Op>
+__device__ inline typename Op::St shfl_st(typename Op::St v, int from) {
+  typename Op::St o;
+  o.m = __shfl(v.m, from);
+  o.s = __shfl(v.s, from);
+  return o;
+}
+
+template <class Op, bool VEC4>
 __global__ __launch_bounds__(256) void k_row_reduce(int64_t nnz, int64_t nitems, int wslots,
                                                     const uint64_t* __restrict__ head,
                                                     const int32_t* __restrict__ tile_row,
@@ -74,81 +107,71 @@ __global__ __launch_bounds__(256) void k_row_reduce(int64_t nnz, int64_t nitems,
                                                     typename Op::St* __restrict__ stats,
                                                     typename Op::St* __restrict__ carry) {
   using St = typename Op::St;
-  __shared__ St s_lead[4][64];
-  __shared__ int s_kind[4][64];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + wv;
-  const bool active = item < nitems;
-  const int S = wslots / 64;
-  int64_t b = 0, e = 0;
-  if (active) {
-    b = item * wslots;
-    e = (b + wslots < nnz) ? b + wslots : nnz;
-  }
-  const int64_t gs = b + (int64_t)lane * S;
-  const int64_t ge = (gs + S < e) ? gs + S : e;
-  St acc = Op::init();
-  int kind = kNone, cur = 0;
-  bool started = false, tail = false;
-  if (active && gs < ge) {
-    cur = row_of_slot(head, tile_row, gs);
-    started = head_at(head, gs);
-    for (int64_t s = gs; s < ge; ++s) {
-      if (s > gs && head_at(head, s)) {
-        if (started) {
-          stats[cur] = acc;
-        } else {
-          s_lead[wv][lane] = acc;
-          kind = kEnds;
-        }
-        acc = Op::init();
-        ++cur;
-        started = true;
-      }
-      Op::push(acc, Op::input(x0, x1, s));
-    }
-    const bool ends = (ge >= nnz) || head_at(head, ge);
-    if (started) {
-      if (ends)
-        stats[cur] = acc;
-      else
-        tail = true;
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= nitems) return;   // uniform per wavefront; no barriers below
+  const int64_t b = item * wslots;
+  const int64_t e = (b + wslots < nnz) ? b + wslots : nnz;
+  const int64_t gs = b + (int64_t)lane * kRun;   // wslots == 64 * kRun
+  const int n = gs < e ? (e - gs < kRun ? (int)(e - gs) : kRun) : 0;
+  const bool ends_at_e = (e >= nnz) || head_at(head, e);
+  St acc = Op::init(), lead = Op::init();
+  bool seen = false;
+  unsigned bits = 0;
+  int cur = 0;
+  if (n > 0) {
+    float x[kRun];
+    if (VEC4 && n == kRun) {
+      Op::template loadv<kRun>(x0, x1, gs, x);
     } else {
-      s_lead[wv][lane] = acc;
-      kind = ends ? kEnds : kThrough;
+#pragma unroll
+      for (int i = 0; i < kRun; ++i) x[i] = i < n ? Op::input(x0, x1, gs + i) : 0.f;
     }
-  }
-  s_kind[wv][lane] = kind;
-  __syncthreads();
-  if (!active) return;
-  if (tail) {
-    bool done = false;
-    for (int l2 = lane + 1; l2 < 64; ++l2) {
-      const int k = s_kind[wv][l2];
-      if (k == kNone) break;
-      acc = Op::merge(acc, s_lead[wv][l2]);
-      if (k == kEnds) {
-        done = true;
-        break;
+    const uint64_t hw = head[gs >> 6];
+    const int sh = (int)(gs & 63);
+    bits = (unsigned)(hw >> sh) & ((1u << n) - 1u);   // n <= kRun <= 16
+    cur = tile_row[gs >> 6] + __popcll(hw & lanemask_le(sh) & ~1ull);
+    seen = bits & 1u;
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) {
+      if (i < n) {
+        if (i > 0 && ((bits >> i) & 1u)) {
+          if (seen)
+            stats[cur] = acc;
+          else
+            lead = acc;
+          acc = Op::init();
+          ++cur;
+          seen = true;
+        }
+        Op::push(acc, x[i]);
       }
     }
-    if (done)
+  }
+  // (P, f): the lane's lead (its whole run when no row starts in it) and
+  // whether a row starts in it.  Sv_l = P_l (+) Sv_{l+1} unless f_l.
+  St sv = seen ? lead : acc;
+  bool F = seen;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const bool inr = lane + d < 64;
+    const int src = inr ? lane + d : lane;
+    const St o = shfl_st<Op>(sv, src);
+    const bool of = __shfl((int)F, src) != 0;
+    if (inr && !F) sv = Op::merge(sv, o);
+    F = F || (inr && of);
+  }
+  const int nsrc = lane < 63 ? lane + 1 : lane;
+  const St nx = shfl_st<Op>(sv, nsrc);
+  const bool nF = (__shfl((int)F, nsrc) != 0) && lane < 63;
+  if (seen) {
+    if (lane < 63) acc = Op::merge(acc, nx);
+    if (nF || ends_at_e)
       stats[cur] = acc;
     else
       carry[item * 2 + 1] = acc;
   }
-  if (lane == 0 && s_kind[wv][0] != kNone) {
-    St hc = s_lead[wv][0];
-    if (s_kind[wv][0] == kThrough) {
-      for (int l2 = 1; l2 < 64; ++l2) {
-        const int k = s_kind[wv][l2];
-        if (k == kNone) break;
-        hc = Op::merge(hc, s_lead[wv][l2]);
-        if (k == kEnds) break;
-      }
-    }
-    carry[item * 2] = hc;
-  }
+  if (lane == 0 && n > 0 && !(bits & 1u)) carry[item * 2] = sv;
 }
 
 template <class Op>
@@ -179,27 +202,71 @@ __global__ __launch_bounds__(256) void k_row_reduce_fixup(int64_t nnz, int64_t n
   if (lane == 0) stats[r] = Op::merge(carry[j * 2 + 1], acc);
 }
 
-__global__ void k_softmax_apply(int64_t nnz, const uint64_t* __restrict__ head,
-                                const int32_t* __restrict__ tile_row,
-                                const SoftmaxStat::St* __restrict__ stats,
-                                const float* __restrict__ e, float* __restrict__ alpha) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const SoftmaxStat::St st = stats[row_of_slot(head, tile_row, p)];
-    alpha[p] = expf(e[p] - st.m) / st.s;
+// The per-entry maps.  A wavefront takes four consecutive 64-slot windows
+// per iteration (grid-stride); lane i takes slot i of each, so every access to
+// the per-entry arrays is coalesced, and the four windows' loads are issued
+// together: two waits per 256 slots (head words and inputs, then row stats).
+constexpr int kApplyWin = 4;
+
+template <class Op>
+__device__ inline void apply_windows(int64_t nnz, const uint64_t* __restrict__ head,
+                                     const int32_t* __restrict__ tile_row,
+                                     const typename Op::St* __restrict__ stats,
+                                     const float* __restrict__ x0, const float* __restrict__ x1,
+                                     float* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwin = (nnz + 63) >> 6;
+  const int64_t ngrp = (nwin + kApplyWin - 1) / kApplyWin;
+  for (int64_t gi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); gi < ngrp;
+       gi += (int64_t)gridDim.x * 4) {
+    int row[kApplyWin];
+    float a[kApplyWin], da[kApplyWin];
+#pragma unroll
+    for (int k = 0; k < kApplyWin; ++k) {
+      const int64_t w = gi * kApplyWin + k;
+      const int64_t wc = w < nwin ? w : nwin - 1;
+      const int64_t p = wc * 64 + lane;
+      const int64_t pc = p < nnz ? p : nnz - 1;
+      row[k] = tile_row[wc] + __popcll(head[wc] & lanemask_le(lane) & ~1ull);
+      a[k] = x0[pc];
+      da[k] = x1 ? x1[pc] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kApplyWin; ++k) {
+      const int64_t p = (gi * kApplyWin + k) * 64 + lane;
+      const typename Op::St st = stats[row[k]];
+      if (p < nnz) y[p] = Op::apply(a[k], da[k], st);
+    }
   }
 }
 
-__global__ void k_softmax_bwd_apply(int64_t nnz, const uint64_t* __restrict__ head,
-                                    const int32_t* __restrict__ tile_row,
-                                    const DotSum::St* __restrict__ stats,
-                                    const float* __restrict__ alpha,
-                                    const float* __restrict__ dalpha, float* __restrict__ de) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const float d = stats[row_of_slot(head, tile_row, p)].s;
-    de[p] = alpha[p] * (dalpha[p] - d);
-  }
+struct SoftmaxApply {
+  using St = SoftmaxStat::St;
+  static __device__ inline float apply(float e, float, St st) { return expf(e - st.m) / st.s; }
+};
+
+struct SoftmaxBwdApply {
+  using St = DotSum::St;
+  static __device__ inline float apply(float a, float da, St st) { return a * (da - st.s); }
+};
+
+__global__ __launch_bounds__(256) void k_softmax_apply(int64_t nnz,
+                                                       const uint64_t* __restrict__ head,
+                                                       const int32_t* __restrict__ tile_row,
+                                                       const SoftmaxStat::St* __restrict__ stats,
+                                                       const float* __restrict__ e,
+                                                       float* __restrict__ alpha) {
+  apply_windows<SoftmaxApply>(nnz, head, tile_row, stats, e, nullptr, alpha);
+}
+
+__global__ __launch_bounds__(256) void k_softmax_bwd_apply(int64_t nnz,
+                                                           const uint64_t* __restrict__ head,
+                                                           const int32_t* __restrict__ tile_row,
+                                                           const DotSum::St* __restrict__ stats,
+                                                           const float* __restrict__ alpha,
+                                                           const float* __restrict__ dalpha,
+                                                           float* __restrict__ de) {
+  apply_windows<SoftmaxBwdApply>(nnz, head, tile_row, stats, alpha, dalpha, de);
 }
 
 __global__ void k_mul_values(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
@@ -211,11 +278,21 @@ __global__ void k_mul_values(int64_t n, const float* __restrict__ a, const float
 
 namespace {
 
-constexpr int kRowItems = 256;   // slots per wavefront work item (4 per lane)
+constexpr int kRowItems = 512;   // slots per wavefront work item (kRun per lane)
+static_assert(kRowItems == 64 * kRun, "one run per lane");
 
 size_t softmax_buffer_bytes(const Plan* p) {
   const int64_t nitems = (p->nnz + kRowItems - 1) / kRowItems;
   return (size_t)(p->R > 0 ? p->R : 1) * 8 + ((size_t)(nitems > 0 ? nitems : 1) * 2) * 8 + 256;
+}
+
+// Workgroups for the apply kernels: one wavefront per kApplyWin windows.
+unsigned apply_blocks(int64_t nnz) {
+  const int64_t waves = ((nnz + 63) / 64 + kApplyWin - 1) / kApplyWin;
+  int64_t b = (waves + 3) / 4;
+  if (b < 1) b = 1;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (unsigned)b;
 }
 
 unsigned blocks_for(int64_t n) {
@@ -234,8 +311,13 @@ spc3d_status row_reduce(const Plan* p, const float* x0, const float* x1, void* b
   const size_t off = (((size_t)(p->R > 0 ? p->R : 1) * 8) + 255) & ~size_t(255);
   St* carry = reinterpret_cast<St*>(static_cast<char*>(buf) + off);
   const unsigned nb = (unsigned)((nitems + 3) / 4);
-  hipLaunchKernelGGL(k_row_reduce<Op>, dim3(nb), dim3(256), 0, stream, p->nnz, nitems,
-                     kRowItems, p->head, p->tile_row, x0, x1, stats, carry);
+  // 16-byte loads of each lane's run where the arrays allow them
+  if (aligned16(x0) && (!x1 || aligned16(x1)))
+    hipLaunchKernelGGL((k_row_reduce<Op, true>), dim3(nb), dim3(256), 0, stream, p->nnz, nitems,
+                       kRowItems, p->head, p->tile_row, x0, x1, stats, carry);
+  else
+    hipLaunchKernelGGL((k_row_reduce<Op, false>), dim3(nb), dim3(256), 0, stream, p->nnz, nitems,
+                       kRowItems, p->head, p->tile_row, x0, x1, stats, carry);
   hipLaunchKernelGGL(k_row_reduce_fixup<Op>, dim3(nb), dim3(256), 0, stream, p->nnz, nitems,
                      kRowItems, p->rowptr, p->head, p->tile_row, stats, carry);
   SPC3D_LAUNCHED("row reduce");
@@ -275,7 +357,7 @@ spc3d_status spc3d_row_softmax(spc3d_plan h, const float* d_e, float* d_alpha, v
   SoftmaxStat::St* stats;
   st = row_reduce<SoftmaxStat>(p, d_e, nullptr, d_buf, stream, &stats);
   if (st != SPC3D_OK) return st;
-  hipLaunchKernelGGL(k_softmax_apply, dim3(blocks_for(p->nnz)), dim3(256), 0, stream, p->nnz,
+  hipLaunchKernelGGL(k_softmax_apply, dim3(apply_blocks(p->nnz)), dim3(256), 0, stream, p->nnz,
                      p->head, p->tile_row, stats, d_e, d_alpha);
   SPC3D_LAUNCHED("softmax apply");
   return SPC3D_OK;
@@ -299,9 +381,27 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan h, const float* d_alpha, const flo
   DotSum::St* stats;
   st = row_reduce<DotSum>(p, d_alpha, d_dalpha, d_buf, stream, &stats);
   if (st != SPC3D_OK) return st;
-  hipLaunchKernelGGL(k_softmax_bwd_apply, dim3(blocks_for(p->nnz)), dim3(256), 0, stream,
+  hipLaunchKernelGGL(k_softmax_bwd_apply, dim3(apply_blocks(p->nnz)), dim3(256), 0, stream,
                      p->nnz, p->head, p->tile_row, stats, d_alpha, d_dalpha, d_de);
   SPC3D_LAUNCHED("softmax bwd apply");
+  return SPC3D_OK;
+}
+
+spc3d_status spc3d_row_softmax_apply(spc3d_plan h, const float* d_e, const float* d_stats,
+                                     float* d_alpha, hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_e || !d_stats || !d_alpha) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_stats) & 7u)
+    return fail(SPC3D_ERR_INVALID_ARG, "stats must be 8-byte aligned");
+  st = use_device(p);
+  if (st != SPC3D_OK) return st;
+  hipLaunchKernelGGL(k_softmax_apply, dim3(apply_blocks(p->nnz)), dim3(256), 0, stream, p->nnz,
+                     p->head, p->tile_row, reinterpret_cast<const SoftmaxStat::St*>(d_stats), d_e,
+                     d_alpha);
+  SPC3D_LAUNCHED("softmax apply");
   return SPC3D_OK;
 }
 

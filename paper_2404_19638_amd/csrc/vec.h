@@ -56,3 +56,32 @@ struct VecLoad<bf16_t, 1> {
 };
 
 }  // namespace spc3d
+
+namespace spc3d {
+
+// Raw 16-byte vectors (4 FP32 or 8 bfloat16), kept unconverted in registers
+// while loads are in flight and converted at use.
+template <typename T, int VEC>
+struct Unpack;
+
+template <>
+struct Unpack<float, 4> {
+  static __device__ inline void run(const uint4& r, float (&o)[4]) {
+    o[0] = __uint_as_float(r.x); o[1] = __uint_as_float(r.y);
+    o[2] = __uint_as_float(r.z); o[3] = __uint_as_float(r.w);
+  }
+};
+
+template <>
+struct Unpack<bf16_t, 8> {
+  static __device__ inline void run(const uint4& r, float (&o)[8]) {
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = __uint_as_float(w[i] << 16);
+      o[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+    }
+  }
+};
+
+}  // namespace spc3d

@@ -75,6 +75,10 @@ def lib():
         "spc3d_row_softmax": [vp, vp, vp, vp, sz, vp],
         "spc3d_row_softmax_bwd": [vp, vp, vp, vp, vp, sz, vp],
         "spc3d_mul_values": [vp, vp, vp, vp, vp],
+        "spc3d_row_softmax_apply": [vp, vp, vp, vp, vp],
+        "spc3d_attention_fwd_buffer_size": [vp, i32, ctypes.c_int, ctypes.c_int, P(sz)],
+        "spc3d_attention_fwd": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int, vp, sz,
+                                vp],
         "spc3d_variant_check": [ctypes.c_int, i32, ctypes.c_int, ctypes.c_int],
         "spc3d_plan_features": [vp, ctypes.c_int, i32, ctypes.c_int, vp, vp, sz, vp],
         "spc3d_mlp_linear_fwd": [ctypes.c_int] * 3 + [vp] * 4 + [ctypes.c_int, vp],
@@ -356,6 +360,68 @@ def row_softmax_bwd(plan: Plan, alpha: torch.Tensor, dalpha: torch.Tensor, out=N
                                        _ptr(buf), buf.numel(), _stream(stream)),
            "spc3d_row_softmax_bwd")
     return out
+
+
+def row_softmax_apply(plan: Plan, e: torch.Tensor, stats: torch.Tensor, out=None, stream=None):
+    """alpha[p] = exp(e[p] - stats[r, 0]) / stats[r, 1] for the entries p of row r."""
+    _need(e.dtype == torch.float32 and e.is_contiguous() and e.numel() >= plan.nnz,
+          "e must hold nnz FP32 values")
+    _need(stats.dtype == torch.float32 and stats.is_contiguous() and stats.numel() >= 2 * plan.R,
+          "stats must hold R (max, sum) FP32 pairs")
+    out = torch.empty_like(e) if out is None else out
+    _check(lib().spc3d_row_softmax_apply(plan.handle, _ptr(e), _ptr(stats), _ptr(out),
+                                         _stream(stream)), "spc3d_row_softmax_apply")
+    return out
+
+
+def attention_fwd_buffer_size(plan: Plan, kz: int, dtype: int = F32, variant: int = -1) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_attention_fwd_buffer_size(plan.handle, kz, dtype, variant,
+                                                 ctypes.byref(b)),
+           "spc3d_attention_fwd_buffer_size")
+    return b.value
+
+
+def attention_supported(kz: int, dtype: int = F32, variant: int = -1) -> bool:
+    """Whether spc3d_attention_fwd covers (kz, dtype, variant) (host-only check)."""
+    nb = kz * (4 if dtype == F32 else 2)
+    if variant >= 0:
+        lanes = 1 << (variant & 15)
+        nvec = nb // 16
+        return nb % 16 == 0 and nvec % lanes == 0 and nvec // lanes in (1, 2)
+    return nb in (64, 128, 256, 512)
+
+
+def attention_fwd(plan: Plan, Q: torch.Tensor, K: torch.Tensor, V: torch.Tensor,
+                  kz: int | None = None, out: torch.Tensor | None = None,
+                  stats: torch.Tensor | None = None, want_stats: bool = True, variant: int = -1,
+                  buf: torch.Tensor | None = None, stream=None):
+    """Fused masked attention forward: out = rowsoftmax(SDDMM(Q, K)) . V in one pass.
+
+    Returns (out [R, kz] FP32, stats [R, 2] FP32 (row max, row sum of exp) or None)."""
+    kz = Q.shape[1] if kz is None else kz
+    _need(Q.dtype == K.dtype == V.dtype, "Q, K and V must share a dtype")
+    _need(Q.is_contiguous() and K.is_contiguous() and V.is_contiguous(),
+          "Q, K and V must be packed (contiguous)")
+    _need(Q.numel() >= plan.R * kz and K.numel() >= plan.C * kz and V.numel() >= plan.C * kz,
+          "Q, K or V too small for kz")
+    if out is None:
+        out = torch.empty((plan.R, kz), dtype=torch.float32, device=Q.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.R * kz,
+          "out too small")
+    if stats is None and want_stats:
+        stats = torch.empty((plan.R, 2), dtype=torch.float32, device=Q.device)
+    if stats is not None:
+        _need(stats.dtype == torch.float32 and stats.is_contiguous()
+              and stats.numel() >= 2 * plan.R, "stats must hold R (max, sum) pairs")
+    dt = _dtype_code(Q)
+    need = attention_fwd_buffer_size(plan, kz, dt, variant)
+    if buf is None:
+        buf = plan.buffer(("attention", kz), need)
+    _check(lib().spc3d_attention_fwd(plan.handle, _ptr(Q), _ptr(K), _ptr(V), dt, kz, _ptr(out),
+                                     _ptr(stats), variant, _ptr(buf), buf.numel(),
+                                     _stream(stream)), "spc3d_attention_fwd")
+    return out, stats
 
 
 def mul_values(plan: Plan, a: torch.Tensor, b: torch.Tensor, out=None, stream=None):

@@ -62,9 +62,12 @@ def _attention_magnitudes(rowptr, colidx, Q, Kf, V, alpha, dout, de):
     return M_out, M_dQ, M_dK, M_dV
 
 
-def test_attention_backward_fd_instance():
+@pytest.mark.parametrize("K,fused", [(8, False), (16, True)])
+def test_attention_backward_fd_instance(K, fused):
+    """K = 8: the three-kernel layer; K = 16: the fused forward, whose backward
+    recomputes the scores and rebuilds alpha from the stored row statistics."""
     spc, ag = _mods()
-    n, nnz, K = 256, 2000, 8
+    n, nnz = 256, 2000
     rows, cols = synth.uniform_block(n, n, nnz, 4242)
     plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
                                (0, n), (0, n), spc.BUILD_CSC)
@@ -77,7 +80,7 @@ def test_attention_backward_fd_instance():
     tq = torch.from_numpy(Q).to(DEV).requires_grad_()
     tk = torch.from_numpy(Kf).to(DEV).requires_grad_()
     tv = torch.from_numpy(V).to(DEV).requires_grad_()
-    out = ag.gnn_attention(plan, tq, tk, tv)
+    out = ag.gnn_attention(plan, tq, tk, tv, fused=fused)
     (out * torch.from_numpy(W).to(DEV)).sum().backward()
     Qd, Kd, Vd, Wd = (x.astype(np.float64) for x in (Q, Kf, V, W))
     e, alpha, o = oracle.attention_fwd(ref["rowptr"], ref["colidx"], Qd, Kd, Vd)
@@ -189,6 +192,15 @@ def test_attention_workload_full_size():
         out = ag.gnn_attention(plan, tq, tk, tv)
         (out * tw).sum().backward()
         tq.grad = tk.grad = tv.grad = None
+    with torch.no_grad():
+        # forward of the one-pass kernel, for comparison with the three-kernel layer
+        ag.gnn_attention(plan, tq, tk, tv, fused=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            out_fused = ag.gnn_attention(plan, tq, tk, tv, fused=True)
+        torch.cuda.synchronize()
+        t_fused = (time.perf_counter() - t0) / 5
     torch.cuda.synchronize()
     reps = 5
     t_f = t_b = 0.0
@@ -215,9 +227,12 @@ def test_attention_workload_full_size():
     de, dQ, _, _ = oracle.attention_bwd(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd)
     M_out, M_dQ, _, _ = _attention_magnitudes(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd, de)
     assert_within_mag(_np(out)[pick], o, M_out, TOL, "attention out (sampled rows)")
+    assert_within_mag(_np(out_fused)[pick], o, M_out, TOL, "fused out (sampled rows)")
     assert_within_mag(_np(tq.grad)[pick], dQ, M_dQ, TOL, "dQ (sampled rows)")
     flops = 2 * 2 * K * p.nnz
     print("ATTENTION_REPORT " + json.dumps({
         "workload": "rmat20-deg32-whole-K64", "nnz": p.nnz, "R": R, "C": C,
+        "forward": "three kernels (SDDMM, row softmax, SpMM)",
         "forward_ms": round(t_f / reps * 1e3, 3), "backward_ms": round(t_b / reps * 1e3, 3),
+        "forward_ms_fused_no_grad": round(t_fused * 1e3, 3),
         "forward_sddmm_spmm_GFLOPs": round(flops / (t_f / reps) / 1e9, 1)}), flush=True)

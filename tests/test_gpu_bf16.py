@@ -149,6 +149,31 @@ def test_precision_workload_full_size():
             gy = _np(Y[torch.from_numpy(loc).long().to(DEV)])
             assert_within_mag(gy, y, my, rel, f"{name} spmm vs {tag}")
             report[f"{name}_spmm_vs_{tag}"] = error_report(gy, y, my)
+        # timing of the same calls (inputs resident, 5 back-to-back calls each)
+        R, C, nnz, nb = plan.R, plan.C, p.nnz, (4 if name == "f32" else 2)
+        alg = {"sddmm": 4 * (R + 1) + 12 * nnz + K * nb * (R + C),
+               "spmm": 4 * (R + 1) + 8 * nnz + K * nb * C + 4 * K * R,
+               "sddmm_spmm": 4 * (R + 1) + 12 * nnz + K * nb * (R + C) + 4 * K * R}
+        calls = {"sddmm": lambda: spc.sddmm(plan, vals, A, B, K, out=out_s),
+                 "spmm": lambda: spc.spmm(plan, vals, B, 0, K, out=Y),
+                 "sddmm_spmm": lambda: spc.sddmm_spmm(plan, vals, A, B, K, out=out, Y=Y)}
+        for op, fn in calls.items():
+            ms = _time_ms(fn)
+            report[f"{name}_{op}_time"] = {"ms": round(ms, 4), "GB_s": round(alg[op] / ms / 1e6, 1),
+                                           "GFLOP_s": round((2 if op != "sddmm_spmm" else 4)
+                                                            * K * nnz / ms / 1e6, 1)}
         del A, B, out, Y, out_s
         torch.cuda.empty_cache()
     print("PRECISION_REPORT " + json.dumps(report), flush=True)
+
+
+def _time_ms(fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
