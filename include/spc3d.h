@@ -268,6 +268,35 @@ spc3d_status spc3d_attention_fwd(spc3d_plan plan, const void* d_Q, const void* d
 spc3d_status spc3d_mul_values(spc3d_plan plan, const float* d_a, const float* d_b, float* d_out,
                               hipStream_t stream);
 
+/* ------------------------------- communication accounting (Dist3D) */
+
+/* Bytes of device workspace spc3d_lambda_owners needs for ids [lo, hi). */
+spc3d_status spc3d_lambda_owners_workspace_size(int64_t lo, int64_t hi, size_t* bytes);
+
+/* lambda counts and Algorithm 1's owner choice for one block row (or column)
+ * of a Dist3D grid (Section "Sparsity-aware Communication Analysis of 3D
+ * SDDMM"; Algorithm 1, "Parallel lambda-aware random distribution").  Part p
+ * (0 <= p < nparts <= 64) uses the h_counts[p] distinct global ids of the
+ * device array h_gmaps[p] (e.g. a plan's gmap_r), all in [lo, hi).  For every
+ * id i in [lo, hi), with j = i - lo:
+ *   d_lambda[j] = number of parts that use i;
+ *   d_owner[j]  = the part of rank floor(d_rand[j] * lambda / 2^64) among
+ *                 them in ascending order (rank 0 when d_rand is NULL), or -1
+ *                 when no part uses i;
+ *   d_owned[p]  = number of ids part p owns;
+ *   d_comm[p*nparts + q] = number of ids part p uses and part q != p owns
+ *                 (the rows p receives from q), 0 on the diagonal.
+ * Integer results, independent of scheduling.  d_rand holds hi - lo 64-bit
+ * random numbers (the caller's seeded draws).  h_gmaps and h_counts are host
+ * arrays of nparts entries.  A setup-time call: it synchronizes the stream
+ * and returns SPC3D_ERR_OUT_OF_RANGE when a part holds an id outside
+ * [lo, hi) (such ids are skipped). */
+spc3d_status spc3d_lambda_owners(int32_t nparts, const int64_t* const* h_gmaps,
+                                 const int64_t* h_counts, int64_t lo, int64_t hi,
+                                 const uint64_t* d_rand, int32_t* d_lambda, int32_t* d_owner,
+                                 int64_t* d_owned, int64_t* d_comm, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
 /* ------------------------------------- learned variant selector (ext.) */
 
 /* Operations a variant is chosen for: spc3d_sddmm, spc3d_spmm (transpose 0)

@@ -63,6 +63,8 @@ def _load():
         lib.oracle_attention_bwd.restype = None
         lib.oracle_attention_bwd.argtypes = [i64, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp,
                                              vp, vp]
+        lib.oracle_lambda_owners.restype = None
+        lib.oracle_lambda_owners.argtypes = [ctypes.c_int, vp, vp, i64, i64, vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -229,3 +231,25 @@ def attention_bwd(rowptr, colidx, Q, Kf, V, alpha, dout):
     _load().oracle_attention_bwd(R, C, _p(rowptr), _p(colidx), K, _p(Q), _p(Kf), _p(V),
                                  _p(alpha), _p(dout), _p(de), _p(dQ), _p(dKf), _p(dV))
     return de[:nnz], dQ[:R], dKf[:C], dV[:C]
+
+
+# ------------------------------------------- lambda and Algorithm 1 owners
+
+def lambda_owners(gmaps, lo, hi, rnd=None) -> dict:
+    """lambda, Algorithm 1 owners, owned counts and the receive matrix of one
+    block row whose part p uses the distinct ids gmaps[p] (see the C source)."""
+    nparts = len(gmaps)
+    arrs = [_c(g, np.int64) for g in gmaps]
+    counts = np.array([a.shape[0] for a in arrs], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * nparts)(*[a.ctypes.data for a in arrs])
+    n = hi - lo
+    lam = np.empty(max(n, 1), np.int32)
+    owner = np.empty(max(n, 1), np.int32)
+    owned = np.empty(nparts, np.int64)
+    comm = np.empty(nparts * nparts, np.int64)
+    r = None if rnd is None else _c(rnd, np.uint64)
+    _load().oracle_lambda_owners(nparts, ctypes.cast(ptrs, ctypes.c_void_p), _p(counts), lo, hi,
+                                 None if r is None else _p(r), _p(lam), _p(owner), _p(owned),
+                                 _p(comm))
+    return dict(lambda_=lam[:n], owner=owner[:n], owned=owned,
+                comm=comm.reshape(nparts, nparts))

@@ -305,3 +305,49 @@ void oracle_attention_bwd(int64_t R, int64_t C, const int32_t* rowptr, const int
     }
   }
 }
+
+/* ------------------------------------------ lambda and Algorithm 1 owners */
+
+/* One block row of a Dist3D grid (Section "Sparsity-aware Communication
+ * Analysis of 3D SDDMM"): part p uses the counts[p] ids gmaps[p][..] of
+ * [lo, hi).  lambda[i-lo] = number of parts using i.  Algorithm 1 gives i to
+ * a uniformly random part among those that use it; with the 64-bit draw r of
+ * the id, the pick is the candidate of rank floor(r * lambda / 2^64) in
+ * ascending part order (rank 0 without draws): a reading of "pick a random
+ * p in candidates" for a given uniform draw.  owned[p] counts the ids part p
+ * owns; comm[p*nparts + q] counts the ids part p uses and part q != p owns
+ * (rows p receives from q).  Brute force over a dense use matrix. */
+void oracle_lambda_owners(int nparts, const int64_t* const* gmaps, const int64_t* counts,
+                          int64_t lo, int64_t hi, const uint64_t* rnd, int32_t* lambda,
+                          int32_t* owner, int64_t* owned, int64_t* comm) {
+  const int64_t n = hi - lo;
+  unsigned char* uses = (unsigned char*)calloc((size_t)(n > 0 ? n : 1) * (size_t)nparts, 1);
+  for (int p = 0; p < nparts; ++p)
+    for (int64_t l = 0; l < counts[p]; ++l) uses[(gmaps[p][l] - lo) * nparts + p] = 1;
+  for (int p = 0; p < nparts; ++p) owned[p] = 0;
+  for (int64_t q = 0; q < (int64_t)nparts * nparts; ++q) comm[q] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int lam = 0;
+    for (int p = 0; p < nparts; ++p) lam += uses[i * nparts + p];
+    lambda[i] = lam;
+    owner[i] = -1;
+    if (lam == 0) continue;
+    const uint64_t k = rnd ? (uint64_t)(((unsigned __int128)rnd[i] * (uint64_t)lam) >> 64) : 0;
+    uint64_t seen = 0;
+    for (int p = 0; p < nparts; ++p) {
+      if (!uses[i * nparts + p]) continue;
+      if (seen == k) {
+        owner[i] = p;
+        break;
+      }
+      ++seen;
+    }
+    owned[owner[i]] += 1;
+  }
+  for (int p = 0; p < nparts; ++p)
+    for (int64_t l = 0; l < counts[p]; ++l) {
+      const int q = owner[gmaps[p][l] - lo];
+      if (q != p) comm[(int64_t)p * nparts + q] += 1;
+    }
+  free(uses);
+}

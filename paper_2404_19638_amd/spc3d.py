@@ -76,6 +76,8 @@ def lib():
         "spc3d_row_softmax_bwd": [vp, vp, vp, vp, vp, sz, vp],
         "spc3d_mul_values": [vp, vp, vp, vp, vp],
         "spc3d_row_softmax_apply": [vp, vp, vp, vp, vp],
+        "spc3d_lambda_owners_workspace_size": [i64, i64, P(sz)],
+        "spc3d_lambda_owners": [i32, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp],
         "spc3d_attention_fwd_buffer_size": [vp, i32, ctypes.c_int, ctypes.c_int, P(sz)],
         "spc3d_attention_fwd": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int, vp, sz,
                                 vp],
@@ -422,6 +424,41 @@ def attention_fwd(plan: Plan, Q: torch.Tensor, K: torch.Tensor, V: torch.Tensor,
                                      _ptr(stats), variant, _ptr(buf), buf.numel(),
                                      _stream(stream)), "spc3d_attention_fwd")
     return out, stats
+
+
+def lambda_owners(gmaps, lo: int, hi: int, rand: torch.Tensor | None = None,
+                  device=None, stream=None) -> dict:
+    """lambda counts and Algorithm 1 owners of ids [lo, hi) over the parts whose
+    distinct ids are the int64 device tensors gmaps[p] (None or empty for a
+    part that uses none).  rand: hi - lo uint64 draws (as int64) or None.
+    Returns device tensors lambda_ (int32), owner (int32), owned (int64, one per
+    part) and comm (int64 [nparts, nparts]: rows part p receives from part q)."""
+    nparts = len(gmaps)
+    _need(1 <= nparts <= 64, "1 to 64 parts")
+    dev = device or next((g.device for g in gmaps if g is not None), torch.device("cuda"))
+    for g in gmaps:
+        if g is not None:
+            _need(g.dtype == torch.int64 and g.is_contiguous(), "gmaps must be int64 contiguous")
+    n = hi - lo
+    if rand is not None:
+        _need(rand.dtype in (torch.int64, torch.uint64) and rand.numel() >= n
+              and rand.is_contiguous(), "rand must hold hi - lo 64-bit draws")
+    ptrs = (ctypes.c_void_p * nparts)(*[None if g is None or g.numel() == 0 else g.data_ptr()
+                                        for g in gmaps])
+    counts = (ctypes.c_int64 * nparts)(*[0 if g is None else g.numel() for g in gmaps])
+    lam = torch.empty(n, dtype=torch.int32, device=dev)
+    owner = torch.empty(n, dtype=torch.int32, device=dev)
+    owned = torch.empty(nparts, dtype=torch.int64, device=dev)
+    comm = torch.empty((nparts, nparts), dtype=torch.int64, device=dev)
+    b = ctypes.c_size_t()
+    _check(lib().spc3d_lambda_owners_workspace_size(lo, hi, ctypes.byref(b)),
+           "spc3d_lambda_owners_workspace_size")
+    ws = torch.empty(b.value, dtype=torch.uint8, device=dev)
+    _check(lib().spc3d_lambda_owners(nparts, ctypes.cast(ptrs, ctypes.c_void_p),
+                                     ctypes.cast(counts, ctypes.c_void_p), lo, hi, _ptr(rand),
+                                     _ptr(lam), _ptr(owner), _ptr(owned), _ptr(comm), _ptr(ws),
+                                     ws.numel(), _stream(stream)), "spc3d_lambda_owners")
+    return dict(lambda_=lam, owner=owner, owned=owned, comm=comm)
 
 
 def mul_values(plan: Plan, a: torch.Tensor, b: torch.Tensor, out=None, stream=None):

@@ -72,6 +72,8 @@ def _load():
                                          i64, i64, i64, i64, pp, pp]
         lib.synth_uniform_block.restype = i64
         lib.synth_uniform_block.argtypes = [i64, i64, i64, u64, i64, i64, pp, pp]
+        lib.synth_draws_u64.restype = None
+        lib.synth_draws_u64.argtypes = [u64, u64, i64, ctypes.c_void_p]
         lib.synth_free.restype = None
         lib.synth_free.argtypes = [ctypes.c_void_p]
         lib.synth_threads.restype = ctypes.c_int
@@ -81,6 +83,13 @@ def _load():
 
 def draw(seed: int, ctr: int) -> int:
     return int(_load().synth_draw(seed, ctr))
+
+
+def draws_u64(seed: int, n: int, ctr0: int = 0) -> np.ndarray:
+    """n raw 64-bit counter draws (seed, ctr0 + i)."""
+    out = np.empty(n, dtype=np.uint64)
+    _load().synth_draws_u64(seed, ctr0, n, out.ctypes.data)
+    return out
 
 
 def uniform_f32(seed: int, n: int, ctr0: int = 0) -> np.ndarray:

@@ -271,3 +271,11 @@ int64_t synth_uniform_block(int64_t nrows, int64_t ncols, int64_t nnz, uint64_t 
 void synth_free(void* p) { free(p); }
 
 int synth_threads(void) { return omp_get_max_threads(); }
+
+/* n raw 64-bit counter draws: out[i] = draw(seed, ctr0 + i) (random numbers a
+ * method consumes, handed to both the GPU path and the oracle). */
+void synth_draws_u64(uint64_t seed, uint64_t ctr0, int64_t n, uint64_t* out) {
+  const uint64_t key = mix64(seed);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = draw(key, ctr0 + (uint64_t)i);
+}
