@@ -283,16 +283,22 @@ def main():
         spans.update(sddmm=(4, 5), spmm=(5, 6), scatter=(6, 7))
 
     def timed(step, steps, warmup):
+        """Step time from exactly `steps` steps with nothing recorded between them
+        (the timing markers of the per-kernel pass add gaps between kernels), then
+        per-kernel times from a second pass with events around every kernel."""
         for _ in range(warmup):
             step()
-        events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)]
-                  for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)]
+                  for _ in range(steps)]
         for i in range(steps):
             step(events[i])
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
         per = {n: float(np.mean([events[i][a].elapsed_time(events[i][b])
                                  for i in range(steps)]))
                for n, (a, b) in spans.items()}
