@@ -126,6 +126,35 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
                                    int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
                                    size_t ws_bytes, hipStream_t stream);
 
+/* spc3d_plan_create_coo with the owner-grouped local order of Method 2
+ * (SpC-SB / SpC-RB) of Section "Sparse communication model": local data
+ * stored as the concatenation of the data units exchanged with each peer, so
+ * that each message is sent or received in place.  d_group_r (int32, one key
+ * per id of [row_lo, row_hi), or NULL for ascending ids) gives every row id a
+ * group in [0, ngroups_r), 1 <= ngroups_r <= 4096 (for example 0 for the rows
+ * this processor owns and 1 + the owner's rank among its peers for the
+ * others); local rows are then the distinct ids ordered by (group, global
+ * id), and the CSR, the maps and every packed buffer follow that order.
+ * Likewise d_group_c / ngroups_c for columns.  Keys of ids the block does not
+ * use are ignored; a used id with a key outside [0, ngroups) gives
+ * INVALID_ARG and no plan.  Same workspace, synchronization and errors as
+ * spc3d_plan_create_coo. */
+spc3d_status spc3d_plan_create_coo_grouped(spc3d_plan* out, int64_t nnz,
+                                           const int64_t* d_row_gid, const int64_t* d_col_gid,
+                                           int64_t row_lo, int64_t row_hi, int64_t col_lo,
+                                           int64_t col_hi, const int32_t* d_group_r,
+                                           int32_t ngroups_r, const int32_t* d_group_c,
+                                           int32_t ngroups_c, uint32_t flags, void* d_ws,
+                                           size_t ws_bytes, hipStream_t stream);
+
+/* Device view of a grouped axis: *d_offsets points at ngroups + 1 int32 in
+ * the plan's workspace, offsets[q] = first local id of group q and
+ * offsets[ngroups] = R (or C): group q occupies local ids [offsets[q],
+ * offsets[q+1]), i.e. rows [offsets[q], offsets[q+1]) of a packed buffer.
+ * INVALID_ARG if the axis was built without groups. */
+spc3d_status spc3d_plan_group_offsets(spc3d_plan plan, spc3d_axis axis,
+                                      const int32_t** d_offsets, int32_t* ngroups);
+
 /* Sizes of a plan: non-empty rows R, non-empty columns C, entries nnz. */
 spc3d_status spc3d_plan_query(spc3d_plan plan, int64_t* R, int64_t* C, int64_t* nnz);
 

@@ -44,6 +44,10 @@ def _load():
         lib.oracle_relabel.restype = ctypes.c_int
         lib.oracle_relabel.argtypes = [i64, vp, vp, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp, vp, vp, vp]
+        lib.oracle_relabel_grouped.restype = ctypes.c_int
+        lib.oracle_relabel_grouped.argtypes = [i64, vp, vp, i64, i64, i64, i64, vp,
+                                               ctypes.c_int32, vp, ctypes.c_int32, vp, vp, vp,
+                                               vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_gather_f32.restype = None
         lib.oracle_gather_f32.argtypes = [i64, vp, i64, vp, i64, i64, i64, vp]
         lib.oracle_gather_bf16.restype = None
@@ -75,14 +79,20 @@ def _c(a, dt):
 
 # ------------------------------------------------------------------ relabel
 
-def relabel(rows, cols, row_range, col_range, csc: bool = False) -> dict:
+def relabel(rows, cols, row_range, col_range, csc: bool = False, group_r=None, ngroups_r=0,
+            group_c=None, ngroups_c=0) -> dict:
     """Localization of a block (paper: Section "Data distribution").
 
     Returns gmap_r, gmap_c (int64), lmap_r, lmap_c, rowptr, colidx, perm
-    (int32) and, with csc=True, colptr, rowidx_t, slot_t.  Raises ValueError
-    on an id outside its range.
+    (int32) and, with csc=True, colptr, rowidx_t, slot_t.  With group_r
+    (int32 key per id of the row range, keys in [0, ngroups_r)) local rows are
+    ordered by (key, global id), the owner-grouped order of SpC-RB; likewise
+    for columns.  Raises ValueError on an id outside its range or a key
+    outside [0, ngroups).
     """
     lib = _load()
+    gr = None if group_r is None else _c(group_r, np.int32)
+    gc = None if group_c is None else _c(group_c, np.int32)
     rows = _c(rows, np.int64)
     cols = _c(cols, np.int64)
     nnz = rows.shape[0]
@@ -102,10 +112,13 @@ def relabel(rows, cols, row_range, col_range, csc: bool = False) -> dict:
         slot_t = np.empty(max(nnz, 1), np.int32)
     R = ctypes.c_int64()
     C = ctypes.c_int64()
-    rc = lib.oracle_relabel(nnz, _p(rows), _p(cols), row_range[0], row_range[1], col_range[0],
-                            col_range[1], ctypes.byref(R), ctypes.byref(C), _p(gmap_r),
-                            _p(gmap_c), _p(lmap_r), _p(lmap_c), _p(rowptr), _p(colidx),
-                            _p(perm), _p(colptr), _p(rowidx_t), _p(slot_t))
+    rc = lib.oracle_relabel_grouped(nnz, _p(rows), _p(cols), row_range[0], row_range[1],
+                                    col_range[0], col_range[1], _p(gr), ngroups_r, _p(gc),
+                                    ngroups_c, ctypes.byref(R), ctypes.byref(C), _p(gmap_r),
+                                    _p(gmap_c), _p(lmap_r), _p(lmap_c), _p(rowptr), _p(colidx),
+                                    _p(perm), _p(colptr), _p(rowidx_t), _p(slot_t))
+    if rc == -2:
+        raise ValueError("group key outside [0, ngroups)")
     if rc != 0:
         raise ValueError("global id outside its range")
     R, C = R.value, C.value

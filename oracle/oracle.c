@@ -74,17 +74,49 @@ static int64_t localize_axis(int64_t nnz, const int64_t* gid, int64_t lo, int64_
  * row-major slot to its caller index.
  * Returns 0, or -1 when an id lies outside its range (outputs undefined).
  */
-int oracle_relabel(int64_t nnz, const int64_t* row_gid, const int64_t* col_gid,
-                   int64_t row_lo, int64_t row_hi, int64_t col_lo, int64_t col_hi,
-                   int64_t* R_out, int64_t* C_out, int64_t* gmap_r, int64_t* gmap_c,
-                   int32_t* lmap_r, int32_t* lmap_c, int32_t* rowptr, int32_t* colidx,
-                   int32_t* perm, int32_t* colptr, int32_t* rowidx_t, int32_t* slot_t) {
+/* Owner-grouped local order (Method 2, SpC-SB/SpC-RB, of Section "Sparse
+ * communication model": local data stored as the concatenation of the data
+ * units exchanged with each peer, so a message lands in one contiguous
+ * piece).  Given a group key per global id, local ids are re-assigned in
+ * order of (key, global id); the maps are rewritten to match.  Returns -1 if
+ * a used id has a key outside [0, ngroups). */
+static int group_axis(int64_t n, int64_t lo, const int32_t* group, int32_t ngroups,
+                      int64_t* gmap, int32_t* lmap) {
+  triple* t = (triple*)malloc(sizeof(triple) * (size_t)(n > 0 ? n : 1));
+  for (int64_t l = 0; l < n; ++l) {
+    const int32_t k = group[gmap[l] - lo];
+    if (k < 0 || k >= ngroups) {
+      free(t);
+      return -1;
+    }
+    t[l].major = k;
+    t[l].minor = gmap[l];
+    t[l].idx = l;
+  }
+  qsort(t, (size_t)n, sizeof(triple), cmp_triple);
+  for (int64_t j = 0; j < n; ++j) {
+    gmap[j] = t[j].minor;
+    lmap[gmap[j] - lo] = (int32_t)j;
+  }
+  free(t);
+  return 0;
+}
+
+int oracle_relabel_grouped(int64_t nnz, const int64_t* row_gid, const int64_t* col_gid,
+                           int64_t row_lo, int64_t row_hi, int64_t col_lo, int64_t col_hi,
+                           const int32_t* group_r, int32_t ngroups_r, const int32_t* group_c,
+                           int32_t ngroups_c, int64_t* R_out, int64_t* C_out, int64_t* gmap_r,
+                           int64_t* gmap_c, int32_t* lmap_r, int32_t* lmap_c, int32_t* rowptr,
+                           int32_t* colidx, int32_t* perm, int32_t* colptr, int32_t* rowidx_t,
+                           int32_t* slot_t) {
   for (int64_t p = 0; p < nnz; ++p) {
     if (row_gid[p] < row_lo || row_gid[p] >= row_hi) return -1;
     if (col_gid[p] < col_lo || col_gid[p] >= col_hi) return -1;
   }
   int64_t R = localize_axis(nnz, row_gid, row_lo, row_hi, gmap_r, lmap_r);
   int64_t C = localize_axis(nnz, col_gid, col_lo, col_hi, gmap_c, lmap_c);
+  if (group_r && group_axis(R, row_lo, group_r, ngroups_r, gmap_r, lmap_r)) return -2;
+  if (group_c && group_axis(C, col_lo, group_c, ngroups_c, gmap_c, lmap_c)) return -2;
   *R_out = R; *C_out = C;
 
   triple* t = (triple*)malloc(sizeof(triple) * (size_t)(nnz > 0 ? nnz : 1));
@@ -122,6 +154,16 @@ int oracle_relabel(int64_t nnz, const int64_t* row_gid, const int64_t* col_gid,
   }
   free(t);
   return 0;
+}
+
+int oracle_relabel(int64_t nnz, const int64_t* row_gid, const int64_t* col_gid,
+                   int64_t row_lo, int64_t row_hi, int64_t col_lo, int64_t col_hi,
+                   int64_t* R_out, int64_t* C_out, int64_t* gmap_r, int64_t* gmap_c,
+                   int32_t* lmap_r, int32_t* lmap_c, int32_t* rowptr, int32_t* colidx,
+                   int32_t* perm, int32_t* colptr, int32_t* rowidx_t, int32_t* slot_t) {
+  return oracle_relabel_grouped(nnz, row_gid, col_gid, row_lo, row_hi, col_lo, col_hi, NULL, 0,
+                                NULL, 0, R_out, C_out, gmap_r, gmap_c, lmap_r, lmap_c, rowptr,
+                                colidx, perm, colptr, rowidx_t, slot_t);
 }
 
 /* ------------------------------------------------------- pack / unpack */

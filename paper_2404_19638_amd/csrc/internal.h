@@ -13,6 +13,7 @@ namespace spc3d {
 constexpr uint64_t kPlanMagic = 0x53504333444c4f43ull;
 constexpr int kMaxKz = 1024;
 constexpr int kMaxKzScalar = 256;
+constexpr int kMaxGroups = 4096;   // owner groups per axis of a grouped plan
 
 // One orientation of the localized block: row-major (CSR) or column-major.
 // Slots are grouped into 64-slot tiles; head[t] bit i is set when slot
@@ -49,6 +50,9 @@ struct Plan {
   int32_t* slot_t = nullptr;
   uint64_t* head_t = nullptr;
   int32_t* tile_col = nullptr;
+  int32_t ngroups_r = 0, ngroups_c = 0;   // owner-grouped local order (0: ascending ids)
+  int32_t* goff_r = nullptr;              // [ngroups + 1] first local id of each group
+  int32_t* goff_c = nullptr;
 
   Orient csr() const {
     Orient o;

@@ -332,6 +332,58 @@ __global__ __launch_bounds__(256) void k_build_slots(int64_t nnz, int64_t nrows,
   }
 }
 
+// ------------------------------------------- owner-grouped local order
+//
+// Method 2 of the paper's sparse communication model (SpC-SB / SpC-RB) stores
+// local data as the concatenation of the data units exchanged with each peer,
+// so that a message is sent or received in place.  With a group key per
+// global id (for example 0 for the rows a processor owns and 1 + peer rank
+// for the others), local ids are re-assigned in order of (key, global id):
+// one stable radix pass over the used ids keyed by the group, whose values
+// are the ids' offsets in the range, then the maps are rewritten.
+
+// keys[l] = group of the l-th used id (in ascending id order), vals[l] = its
+// offset in the range; a key outside [0, ngroups) raises *err.
+__global__ void k_group_keys(int64_t n, const int64_t* __restrict__ gmap, int64_t lo,
+                             const int32_t* __restrict__ group, int32_t ngroups,
+                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                             int32_t* __restrict__ err) {
+  for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n;
+       l += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t off = gmap[l] - lo;
+    const int32_t k = group[off];
+    const bool ok = k >= 0 && k < ngroups;
+    if (!ok) err[0] = 1;
+    keys[l] = ok ? (uint64_t)k : 0ull;
+    vals[l] = (int32_t)off;
+  }
+}
+
+// New local id j for the id at range offset sv[j].
+__global__ void k_apply_order(int64_t n, const int32_t* __restrict__ sv, int64_t lo,
+                              int64_t* __restrict__ gmap, int32_t* __restrict__ lmap) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t off = sv[j];
+    gmap[j] = lo + off;
+    lmap[off] = (int32_t)j;
+  }
+}
+
+// goff[q] = number of used ids with key < q, for q = 0..ngroups (sorted keys).
+__global__ void k_group_offsets(int32_t ngroups, int64_t n, const uint64_t* __restrict__ sk,
+                                int32_t* __restrict__ goff) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q <= ngroups;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = 0, b = n;
+    while (a < b) {
+      const int64_t m = (a + b) >> 1;
+      if (sk[m] < (uint64_t)q) a = m + 1; else b = m;
+    }
+    goff[q] = (int32_t)a;
+  }
+}
+
 __global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, int dir,
                           const float* __restrict__ in, float* __restrict__ out) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
@@ -365,7 +417,7 @@ struct Bump {
 
 struct Layout {
   size_t gmap_r, gmap_c, lmap_r, lmap_c, rowptr, colidx, perm, head, tile_row;
-  size_t colptr, rowidx_t, slot_t, head_t, tile_col, small;
+  size_t colptr, rowidx_t, slot_t, head_t, tile_col, small, goff_r, goff_c;
   size_t keys0, keys1, vals0, vals1, counts, partial;
   size_t total;
   int64_t sort_blocks, partial_len;
@@ -393,6 +445,8 @@ Layout make_layout(int64_t nnz, int64_t rr, int64_t cr, uint32_t flags) {
   L.head_t = csc ? b.take(8 * (size_t)ntiles) : 0;
   L.tile_col = csc ? b.take(4 * (size_t)ntiles) : 0;
   L.small = b.take(256);
+  L.goff_r = b.take(4 * (size_t)(kMaxGroups + 1));
+  L.goff_c = b.take(4 * (size_t)(kMaxGroups + 1));
   // temporaries (dead after plan creation)
   L.sort_blocks = (nnz + kSortTile - 1) / kSortTile;
   L.keys0 = b.take(8 * (size_t)nnz);
@@ -464,6 +518,33 @@ spc3d_status radix_sort(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, in
   return SPC3D_OK;
 }
 
+// Re-assigns the local ids of one axis in (group, id) order (see above).
+spc3d_status group_axis(int64_t n, int64_t lo, int64_t* gmap, int32_t* lmap,
+                        const int32_t* group, int32_t ngroups, int32_t* goff, uint64_t* k0,
+                        int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* counts,
+                        int32_t* partial, int32_t* d_err, hipStream_t s) {
+  if (n > 0) {
+    hipLaunchKernelGGL(k_group_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, n, gmap, lo, group,
+                       ngroups, k0, v0, d_err);
+    SPC3D_LAUNCHED("group keys");
+    uint64_t* sk;
+    int32_t* sv;
+    const int64_t nblk = (n + kSortTile - 1) / kSortTile;
+    spc3d_status st = radix_sort(k0, v0, k1, v1, n, ceil_log2(ngroups), counts, nblk, partial,
+                                 s, &sk, &sv);
+    if (st != SPC3D_OK) return st;
+    hipLaunchKernelGGL(k_apply_order, dim3(grid_for(n, 256)), dim3(256), 0, s, n, sv, lo, gmap,
+                       lmap);
+    hipLaunchKernelGGL(k_group_offsets, dim3(grid_for(ngroups + 1, 256)), dim3(256), 0, s,
+                       ngroups, n, sk, goff);
+  } else {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(ngroups + 1, 256)), dim3(256), 0, s, goff,
+                       (int64_t)ngroups + 1, 0);
+  }
+  SPC3D_LAUNCHED("group order");
+  return SPC3D_OK;
+}
+
 spc3d_status validate_ranges(int64_t nnz, int64_t row_lo, int64_t row_hi, int64_t col_lo,
                              int64_t col_hi) {
   if (nnz < 0 || nnz > INT32_MAX - 64)
@@ -492,10 +573,15 @@ spc3d_status spc3d_plan_workspace_size(int64_t nnz, int64_t row_lo, int64_t row_
   return SPC3D_OK;
 }
 
-spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
-                                   const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
-                                   int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
-                                   size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+spc3d_status create_plan(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
+                         const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                         int64_t col_lo, int64_t col_hi, const int32_t* d_group_r,
+                         int32_t ngroups_r, const int32_t* d_group_c, int32_t ngroups_c,
+                         uint32_t flags, void* d_ws, size_t ws_bytes, hipStream_t stream) {
   if (!out) return fail(SPC3D_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   spc3d_status st = validate_ranges(nnz, row_lo, row_hi, col_lo, col_hi);
@@ -544,6 +630,14 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
   int32_t* vals1 = reinterpret_cast<int32_t*>(w + L.vals1);
   int32_t* counts = reinterpret_cast<int32_t*>(w + L.counts);
   int32_t* partial = reinterpret_cast<int32_t*>(w + L.partial);
+  if (d_group_r) {
+    p->ngroups_r = ngroups_r;
+    p->goff_r = reinterpret_cast<int32_t*>(w + L.goff_r);
+  }
+  if (d_group_c) {
+    p->ngroups_c = ngroups_c;
+    p->goff_c = reinterpret_cast<int32_t*>(w + L.goff_c);
+  }
 
   auto bail = [&](spc3d_status s) {
     delete p;
@@ -565,6 +659,23 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
     return bail(fail(SPC3D_ERR_OUT_OF_RANGE, "a global id lies outside its [lo, hi) range"));
   p->R = host_small[0];
   p->C = host_small[1];
+  if (d_group_r || d_group_c) {
+    if (d_group_r) {
+      st = group_axis(p->R, row_lo, p->gmap_r, p->lmap_r, d_group_r, ngroups_r, p->goff_r, keys0,
+                      vals0, keys1, vals1, counts, partial, small + 3, stream);
+      if (st != SPC3D_OK) return bail(st);
+    }
+    if (d_group_c) {
+      st = group_axis(p->C, col_lo, p->gmap_c, p->lmap_c, d_group_c, ngroups_c, p->goff_c, keys0,
+                      vals0, keys1, vals1, counts, partial, small + 3, stream);
+      if (st != SPC3D_OK) return bail(st);
+    }
+    int32_t host_err = 0;
+    e = hipMemcpyAsync(&host_err, small + 3, sizeof host_err, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "plan_create group sync"));
+    if (host_err) return bail(fail(SPC3D_ERR_INVALID_ARG, "a group key lies outside [0, ngroups)"));
+  }
 
   const int bits_r = ceil_log2(p->R), bits_c = ceil_log2(p->C);
   if (nnz > 0) {
@@ -612,6 +723,46 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
     g_plans.insert(static_cast<const void*>(p));
   }
   *out = reinterpret_cast<spc3d_plan>(p);
+  return SPC3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
+                                   const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                                   int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+  return create_plan(out, nnz, d_row_gid, d_col_gid, row_lo, row_hi, col_lo, col_hi, nullptr, 0,
+                     nullptr, 0, flags, d_ws, ws_bytes, stream);
+}
+
+spc3d_status spc3d_plan_create_coo_grouped(spc3d_plan* out, int64_t nnz,
+                                           const int64_t* d_row_gid, const int64_t* d_col_gid,
+                                           int64_t row_lo, int64_t row_hi, int64_t col_lo,
+                                           int64_t col_hi, const int32_t* d_group_r,
+                                           int32_t ngroups_r, const int32_t* d_group_c,
+                                           int32_t ngroups_c, uint32_t flags, void* d_ws,
+                                           size_t ws_bytes, hipStream_t stream) {
+  if (out) *out = nullptr;
+  if ((d_group_r && (ngroups_r < 1 || ngroups_r > kMaxGroups)) ||
+      (d_group_c && (ngroups_c < 1 || ngroups_c > kMaxGroups)))
+    return fail(SPC3D_ERR_INVALID_ARG, "ngroups must lie in [1, %d]", kMaxGroups);
+  return create_plan(out, nnz, d_row_gid, d_col_gid, row_lo, row_hi, col_lo, col_hi, d_group_r,
+                     ngroups_r, d_group_c, ngroups_c, flags, d_ws, ws_bytes, stream);
+}
+
+spc3d_status spc3d_plan_group_offsets(spc3d_plan h, spc3d_axis axis, const int32_t** d_offsets,
+                                      int32_t* ngroups) {
+  Plan* p;
+  spc3d_status st = get_plan(h, &p);
+  if (st != SPC3D_OK) return st;
+  if (axis != SPC3D_ROWS && axis != SPC3D_COLS) return fail(SPC3D_ERR_INVALID_ARG, "bad axis");
+  const int32_t* g = axis == SPC3D_ROWS ? p->goff_r : p->goff_c;
+  if (!g) return fail(SPC3D_ERR_INVALID_ARG, "the plan was built without groups on this axis");
+  if (d_offsets) *d_offsets = g;
+  if (ngroups) *ngroups = axis == SPC3D_ROWS ? p->ngroups_r : p->ngroups_c;
   return SPC3D_OK;
 }
 

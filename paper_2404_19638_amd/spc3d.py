@@ -59,6 +59,9 @@ def lib():
     sigs = {
         "spc3d_plan_workspace_size": [i64, i64, i64, i64, i64, u32, P(sz)],
         "spc3d_plan_create_coo": [P(vp), i64, vp, vp, i64, i64, i64, i64, u32, vp, sz, vp],
+        "spc3d_plan_create_coo_grouped": [P(vp), i64, vp, vp, i64, i64, i64, i64, vp, i32, vp,
+                                          i32, u32, vp, sz, vp],
+        "spc3d_plan_group_offsets": [vp, ctypes.c_int, P(vp), P(i32)],
         "spc3d_plan_query": [vp, P(i64), P(i64), P(i64)],
         "spc3d_plan_maps": [vp, vp],
         "spc3d_plan_destroy": [vp],
@@ -179,6 +182,14 @@ class Plan:
                        slot_t=self._view(m.slot_t, self.nnz, torch.int32))
         return out
 
+    def group_offsets(self, axis: int) -> torch.Tensor:
+        """Device view of the ngroups + 1 first local ids of a grouped axis."""
+        d = ctypes.c_void_p()
+        ng = ctypes.c_int32()
+        _check(lib().spc3d_plan_group_offsets(self.handle, axis, ctypes.byref(d), ctypes.byref(ng)),
+               "spc3d_plan_group_offsets")
+        return self._view(d.value, ng.value + 1, torch.int32)
+
     def buffer(self, key, nbytes):
         """Cached 256-byte aligned scratch tensor (torch allocations are aligned)."""
         b = self._bufs.get(key)
@@ -206,19 +217,35 @@ def plan_workspace_size(nnz, row_lo, row_hi, col_lo, col_hi, flags=0) -> int:
 
 
 def plan_create_coo(row_gid: torch.Tensor, col_gid: torch.Tensor, row_range, col_range,
-                    flags: int = 0, ws: torch.Tensor | None = None, stream=None) -> Plan:
-    """Localize a COO block of int64 global ids (device tensors).  Synchronizes."""
+                    flags: int = 0, ws: torch.Tensor | None = None, stream=None,
+                    group_r: torch.Tensor | None = None, ngroups_r: int = 0,
+                    group_c: torch.Tensor | None = None, ngroups_c: int = 0) -> Plan:
+    """Localize a COO block of int64 global ids (device tensors).  Synchronizes.
+
+    With group_r (int32 device tensor, one key per id of the row range, keys
+    in [0, ngroups_r)) local rows are ordered by (key, global id) -- the
+    owner-grouped order (spc3d_plan_create_coo_grouped); likewise group_c."""
     assert row_gid.dtype == torch.int64 and col_gid.dtype == torch.int64
     assert row_gid.is_contiguous() and col_gid.is_contiguous()
+    for g, rng in ((group_r, row_range), (group_c, col_range)):
+        if g is not None:
+            _need(g.dtype == torch.int32 and g.is_contiguous() and g.numel() >= rng[1] - rng[0],
+                  "group keys: int32, one per id of the range")
     nnz = row_gid.numel()
     need = plan_workspace_size(nnz, row_range[0], row_range[1], col_range[0], col_range[1], flags)
     if ws is None:
         ws = torch.empty(need, dtype=torch.uint8, device=row_gid.device)
     h = ctypes.c_void_p()
-    _check(lib().spc3d_plan_create_coo(ctypes.byref(h), nnz, _ptr(row_gid), _ptr(col_gid),
-                                       row_range[0], row_range[1], col_range[0], col_range[1],
-                                       flags, _ptr(ws), ws.numel(), _stream(stream)),
-           "spc3d_plan_create_coo")
+    if group_r is None and group_c is None:
+        _check(lib().spc3d_plan_create_coo(ctypes.byref(h), nnz, _ptr(row_gid), _ptr(col_gid),
+                                           row_range[0], row_range[1], col_range[0],
+                                           col_range[1], flags, _ptr(ws), ws.numel(),
+                                           _stream(stream)), "spc3d_plan_create_coo")
+    else:
+        _check(lib().spc3d_plan_create_coo_grouped(
+            ctypes.byref(h), nnz, _ptr(row_gid), _ptr(col_gid), row_range[0], row_range[1],
+            col_range[0], col_range[1], _ptr(group_r), ngroups_r, _ptr(group_c), ngroups_c,
+            flags, _ptr(ws), ws.numel(), _stream(stream)), "spc3d_plan_create_coo_grouped")
     return Plan(h, ws, row_range, col_range, flags)
 
 
