@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2405)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
+    ap.add_argument("--row-groups", type=int, default=0, metavar="G",
+                    help="owner-grouped local rows (SpC-RB order): seeded keys in [0, G)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -221,7 +223,12 @@ def main():
 
     # setup phase (once per pattern), timed separately
     t0 = time.perf_counter()
-    plan = spc.plan_create_coo(rows, cols, p.row_range, p.col_range)
+    groups = {}
+    if args.row_groups:
+        rr = p.row_range[1] - p.row_range[0]
+        keys = (synth.draws_u64(args.seed + 3, rr) % np.uint64(args.row_groups)).astype(np.int32)
+        groups = dict(group_r=torch.from_numpy(keys).to(dev), ngroups_r=args.row_groups)
+    plan = spc.plan_create_coo(rows, cols, p.row_range, p.col_range, **groups)
     vals = spc.permute_values(plan, spc.CALLER_TO_SLOT, vals_caller)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
@@ -335,7 +342,9 @@ def main():
         "config": {"workload": workload, "rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4",
                    "block": [5, 2], "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
                    "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
-                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce")},
+                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce"),
+                   "local_row_order": (f"owner-grouped, {args.row_groups} groups"
+                                       if args.row_groups else "ascending global id")},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
