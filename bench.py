@@ -105,6 +105,26 @@ ERROR_BARS = {
 SELECTOR_WEIGHTS = os.path.join(ROOT, "paper_2404_19638_amd", "selector_weights.json")
 
 
+def copy_bandwidth(dev, mib=1024, reps=10):
+    """GB/s of a plain device-to-device copy of `mib` MiB (read + write bytes)."""
+    import torch
+    n = mib << 18
+    a = torch.ones(n, device=dev)
+    c = torch.empty_like(a)
+    for _ in range(2):
+        c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def cold_kernels(step, names, spans, nev, alg, steps, dev):
     """Per-kernel event times with L2 and the Infinity Cache flushed before
     each step by a 1 GiB write (the flush itself is outside the events)."""
@@ -326,6 +346,9 @@ def main():
                    "frac_hbm": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for n in names}
     total_alg = sum(alg[n] for n in names)
+    copy_gbs = copy_bandwidth(dev)
+    for n in names:
+        kernels[n]["frac_copy"] = round(kernels[n]["GB_s"] / copy_gbs, 4)
     res = {
         "metric": "SDDMM+SpMM GFLOP/s",
         "value": round(value, 2),
@@ -350,6 +373,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(dominant, workload, src_hash)},
         "step_frac_hbm": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_GB_s": round(copy_gbs, 1),
+        "step_frac_copy": round(total_alg / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
         "kernels": kernels,
         "setup_ms": round(setup_ms, 2),
         "source_hash": src_hash,
