@@ -126,6 +126,19 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
                                    int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
                                    size_t ws_bytes, hipStream_t stream);
 
+/* spc3d_plan_create_coo for a block given in CSR with global ids:
+ * d_rowptr[row_hi - row_lo + 1] (int64) over every global row of the range
+ * (rows without entries included), d_rowptr[0] = 0 and d_rowptr[last] =
+ * nnz; d_col_gid[nnz] the int64 global column ids in row order.  The
+ * "caller order" of values and of perm is the CSR entry order.  Same
+ * workspace (spc3d_plan_workspace_size with this nnz), synchronization and
+ * errors as spc3d_plan_create_coo, plus INVALID_ARG for a row pointer that
+ * does not start at 0, decreases, or does not end at nnz. */
+spc3d_status spc3d_plan_create_csr(spc3d_plan* out, int64_t nnz, const int64_t* d_rowptr,
+                                   const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                                   int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
 /* spc3d_plan_create_coo with the owner-grouped local order of Method 2
  * (SpC-SB / SpC-RB) of Section "Sparse communication model": local data
  * stored as the concatenation of the data units exchanged with each peer, so

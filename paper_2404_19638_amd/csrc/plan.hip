@@ -332,6 +332,35 @@ __global__ __launch_bounds__(256) void k_build_slots(int64_t nnz, int64_t nrows,
   }
 }
 
+// ------------------------------------------------------- CSR input
+
+// rows[p] = lo + i for the entries p in [rowptr[i], rowptr[i+1]) (binary
+// search per entry; a non-monotone rowptr only raises *err, every id stays in
+// the range).
+__global__ void k_csr_rows(int64_t n, const int64_t* __restrict__ rowptr, int64_t nnz, int64_t lo,
+                           int64_t* __restrict__ rows) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = 0, b = n;   // largest i in [0, n) with rowptr[i] <= p
+    while (b - a > 1) {
+      const int64_t m = (a + b) >> 1;
+      if (rowptr[m] <= p) a = m; else b = m;
+    }
+    rows[p] = lo + a;
+  }
+}
+
+__global__ void k_csr_check(int64_t n, const int64_t* __restrict__ rowptr, int64_t nnz,
+                            int32_t* __restrict__ err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = rowptr[i];
+    if ((i == 0 && v != 0) || (i == n && v != nnz) || (i < n && rowptr[i + 1] < v) || v < 0 ||
+        v > nnz)
+      err[0] = 1;
+  }
+}
+
 // ------------------------------------------- owner-grouped local order
 //
 // Method 2 of the paper's sparse communication model (SpC-SB / SpC-RB) stores
@@ -435,8 +464,10 @@ Layout make_layout(int64_t nnz, int64_t rr, int64_t cr, uint32_t flags) {
   L.lmap_r = b.take(4 * (size_t)rr);
   L.lmap_c = b.take(4 * (size_t)cr);
   L.rowptr = b.take(4 * (size_t)(cap_r + 1));
-  L.colidx = b.take(4 * (size_t)nnz);
-  L.perm = b.take(4 * (size_t)nnz);
+  // colidx and perm are one region: before the slots are built it holds the
+  // int64 row ids expanded from a CSR input (plan_create_csr)
+  L.colidx = b.take(8 * (size_t)nnz);
+  L.perm = L.colidx + 4 * (size_t)nnz;
   L.head = b.take(8 * (size_t)ntiles);
   L.tile_row = b.take(4 * (size_t)ntiles);
   L.colptr = csc ? b.take(4 * (size_t)(cap_c + 1)) : 0;
@@ -578,7 +609,8 @@ spc3d_status spc3d_plan_workspace_size(int64_t nnz, int64_t row_lo, int64_t row_
 namespace {
 
 spc3d_status create_plan(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
-                         const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                         const int64_t* d_rowptr, const int64_t* d_col_gid, int64_t row_lo,
+                         int64_t row_hi,
                          int64_t col_lo, int64_t col_hi, const int32_t* d_group_r,
                          int32_t ngroups_r, const int32_t* d_group_c, int32_t ngroups_c,
                          uint32_t flags, void* d_ws, size_t ws_bytes, hipStream_t stream) {
@@ -587,7 +619,7 @@ spc3d_status create_plan(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
   spc3d_status st = validate_ranges(nnz, row_lo, row_hi, col_lo, col_hi);
   if (st != SPC3D_OK) return st;
   if (flags & ~uint32_t(SPC3D_BUILD_CSC)) return fail(SPC3D_ERR_INVALID_ARG, "unknown flags");
-  if (nnz > 0 && (!d_row_gid || !d_col_gid))
+  if (nnz > 0 && ((!d_row_gid && !d_rowptr) || !d_col_gid))
     return fail(SPC3D_ERR_INVALID_ARG, "id arrays are NULL");
   if (!d_ws) return fail(SPC3D_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) & 255u)
@@ -644,17 +676,33 @@ spc3d_status create_plan(spc3d_plan* out, int64_t nnz, const int64_t* d_row_gid,
     return s;
   };
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, small, (int64_t)64, 0);
+  if (d_rowptr) {
+    // CSR input: check the row pointer, expand it to one row id per entry in
+    // the colidx / perm region (free until the slots are built)
+    hipLaunchKernelGGL(k_csr_check, dim3(grid_for(rr + 1, 256)), dim3(256), 0, stream, rr,
+                       d_rowptr, nnz, small + 4);
+    if (nnz > 0) {
+      int64_t* rows_tmp = reinterpret_cast<int64_t*>(w + L.colidx);
+      hipLaunchKernelGGL(k_csr_rows, dim3(grid_for(nnz, 256)), dim3(256), 0, stream, rr, d_rowptr,
+                         nnz, row_lo, rows_tmp);
+      d_row_gid = rows_tmp;
+    }
+    SPC3D_LAUNCHED("csr rows");
+  }
   st = localize(nnz, d_row_gid, row_lo, rr, p->lmap_r, p->gmap_r, partial, small + 0,
                 small + 2, stream);
   if (st != SPC3D_OK) return bail(st);
   st = localize(nnz, d_col_gid, col_lo, cr, p->lmap_c, p->gmap_c, partial, small + 1,
                 small + 2, stream);
   if (st != SPC3D_OK) return bail(st);
-  int32_t host_small[4] = {0, 0, 0, 0};
+  int32_t host_small[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipError_t e = hipMemcpyAsync(host_small, small, sizeof host_small, hipMemcpyDeviceToHost,
                                 stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return bail(hip_fail(e, "plan_create sync"));
+  if (host_small[4])
+    return bail(fail(SPC3D_ERR_INVALID_ARG,
+                     "rowptr must start at 0, not decrease, and end at nnz"));
   if (host_small[2])
     return bail(fail(SPC3D_ERR_OUT_OF_RANGE, "a global id lies outside its [lo, hi) range"));
   p->R = host_small[0];
@@ -734,8 +782,18 @@ spc3d_status spc3d_plan_create_coo(spc3d_plan* out, int64_t nnz, const int64_t* 
                                    const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
                                    int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
                                    size_t ws_bytes, hipStream_t stream) {
-  return create_plan(out, nnz, d_row_gid, d_col_gid, row_lo, row_hi, col_lo, col_hi, nullptr, 0,
-                     nullptr, 0, flags, d_ws, ws_bytes, stream);
+  return create_plan(out, nnz, d_row_gid, nullptr, d_col_gid, row_lo, row_hi, col_lo, col_hi,
+                     nullptr, 0, nullptr, 0, flags, d_ws, ws_bytes, stream);
+}
+
+spc3d_status spc3d_plan_create_csr(spc3d_plan* out, int64_t nnz, const int64_t* d_rowptr,
+                                   const int64_t* d_col_gid, int64_t row_lo, int64_t row_hi,
+                                   int64_t col_lo, int64_t col_hi, uint32_t flags, void* d_ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+  if (out) *out = nullptr;
+  if (!d_rowptr) return fail(SPC3D_ERR_INVALID_ARG, "rowptr is NULL");
+  return create_plan(out, nnz, nullptr, d_rowptr, d_col_gid, row_lo, row_hi, col_lo, col_hi,
+                     nullptr, 0, nullptr, 0, flags, d_ws, ws_bytes, stream);
 }
 
 spc3d_status spc3d_plan_create_coo_grouped(spc3d_plan* out, int64_t nnz,
@@ -749,8 +807,8 @@ spc3d_status spc3d_plan_create_coo_grouped(spc3d_plan* out, int64_t nnz,
   if ((d_group_r && (ngroups_r < 1 || ngroups_r > kMaxGroups)) ||
       (d_group_c && (ngroups_c < 1 || ngroups_c > kMaxGroups)))
     return fail(SPC3D_ERR_INVALID_ARG, "ngroups must lie in [1, %d]", kMaxGroups);
-  return create_plan(out, nnz, d_row_gid, d_col_gid, row_lo, row_hi, col_lo, col_hi, d_group_r,
-                     ngroups_r, d_group_c, ngroups_c, flags, d_ws, ws_bytes, stream);
+  return create_plan(out, nnz, d_row_gid, nullptr, d_col_gid, row_lo, row_hi, col_lo, col_hi,
+                     d_group_r, ngroups_r, d_group_c, ngroups_c, flags, d_ws, ws_bytes, stream);
 }
 
 spc3d_status spc3d_plan_group_offsets(spc3d_plan h, spc3d_axis axis, const int32_t** d_offsets,

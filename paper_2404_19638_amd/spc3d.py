@@ -59,6 +59,7 @@ def lib():
     sigs = {
         "spc3d_plan_workspace_size": [i64, i64, i64, i64, i64, u32, P(sz)],
         "spc3d_plan_create_coo": [P(vp), i64, vp, vp, i64, i64, i64, i64, u32, vp, sz, vp],
+        "spc3d_plan_create_csr": [P(vp), i64, vp, vp, i64, i64, i64, i64, u32, vp, sz, vp],
         "spc3d_plan_create_coo_grouped": [P(vp), i64, vp, vp, i64, i64, i64, i64, vp, i32, vp,
                                           i32, u32, vp, sz, vp],
         "spc3d_plan_group_offsets": [vp, ctypes.c_int, P(vp), P(i32)],
@@ -246,6 +247,27 @@ def plan_create_coo(row_gid: torch.Tensor, col_gid: torch.Tensor, row_range, col
             ctypes.byref(h), nnz, _ptr(row_gid), _ptr(col_gid), row_range[0], row_range[1],
             col_range[0], col_range[1], _ptr(group_r), ngroups_r, _ptr(group_c), ngroups_c,
             flags, _ptr(ws), ws.numel(), _stream(stream)), "spc3d_plan_create_coo_grouped")
+    return Plan(h, ws, row_range, col_range, flags)
+
+
+def plan_create_csr(rowptr: torch.Tensor, col_gid: torch.Tensor, row_range, col_range,
+                    flags: int = 0, ws: torch.Tensor | None = None, stream=None) -> Plan:
+    """Localize a block given in CSR over its global row range: int64 rowptr
+    (one entry per row of the range, plus one) and int64 global column ids in
+    row order (device tensors).  Synchronizes."""
+    assert rowptr.dtype == torch.int64 and col_gid.dtype == torch.int64
+    assert rowptr.is_contiguous() and col_gid.is_contiguous()
+    _need(rowptr.numel() == row_range[1] - row_range[0] + 1,
+          "rowptr needs one entry per row of the range, plus one")
+    nnz = col_gid.numel()
+    need = plan_workspace_size(nnz, row_range[0], row_range[1], col_range[0], col_range[1], flags)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=col_gid.device)
+    h = ctypes.c_void_p()
+    _check(lib().spc3d_plan_create_csr(ctypes.byref(h), nnz, _ptr(rowptr), _ptr(col_gid),
+                                       row_range[0], row_range[1], col_range[0], col_range[1],
+                                       flags, _ptr(ws), ws.numel(), _stream(stream)),
+           "spc3d_plan_create_csr")
     return Plan(h, ws, row_range, col_range, flags)
 
 
