@@ -671,7 +671,11 @@ __global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int6
 
 // Rows cut by item boundaries: item j whose last row starts inside it and
 // continues past its end owns the row; it adds its tail carry and the head
-// carries of the items the row runs through, in item order.
+// carries of the items the row runs through, in item order.  One round of
+// independent loads serves the common case (the row ends in item j + 1): the
+// head words of items j and j + 1 and the first word of j + 2 (one per lane),
+// the tile row of slot e - 1, j's tail carry and j + 1's head carry.  Only a
+// row that runs past item j + 1 reads the row pointer and more carries.
 template <int VEC, int LPN, int NCH>
 __global__ __launch_bounds__(256) void k_spmm_fixup(int64_t nnz, int64_t nitems, int wslots,
                                                     const int32_t* __restrict__ ptr,
@@ -683,43 +687,68 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(int64_t nnz, int64_t nitems,
   constexpr int BLK = 16;
   const int lane = threadIdx.x & 63, g = lane / LPN, q = lane % LPN;
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= nitems) return;
+  if (j >= nitems) return;   // uniform per wavefront, as are the returns below
   const int64_t b = j * wslots, e = b + wslots;
-  if (e >= nnz || is_head(head, e)) return;
-  const int r = row_of(head, tile_row, e - 1);
-  if (ptr[r] < b) return;
-  const int64_t jl = ((int64_t)ptr[r + 1] - 1) / wslots;
+  if (e >= nnz) return;      // the last item ends with the block
+  const int nw = wslots >> 6;   // head words per item (wslots <= 1024: 2 nw + 1 <= 33 lanes)
   const int nvec = kz / VEC;
+  const int64_t ntiles = (nnz + 63) >> 6;
+  const int64_t wi = (b >> 6) + lane;
+  const uint64_t hw = (lane <= 2 * nw && wi < ntiles) ? head[wi] : 0ull;
+  const int trow = tile_row[(e - 1) >> 6];
+  float tail[NCH][VEC], nxt[NCH][VEC];
+  zero(tail);
+  zero(nxt);
+  add_vec<VEC, NCH>(carry + (j * 2 + 1) * kz, nvec, q, LPN, tail);
+  add_vec<VEC, NCH>(carry + ((j + 1) * 2) * kz, nvec, q, LPN, nxt);
+  if (__shfl(hw, nw) & 1ull) return;               // slot e starts a row
+  if (!__any(lane < nw && hw != 0ull)) return;     // the row of slot e - 1 began before b
+  const int r = trow + __popcll(__shfl(hw, nw - 1) & ~1ull);   // row of slot e - 1
+  // the item holding the row's last slot: from the first row start after e
+  const uint64_t found = __ballot(lane >= nw && lane <= 2 * nw && hw != 0ull);
+  int64_t jl;
+  if (found) {
+    const int f = __ffsll((long long)found) - 1;
+    const uint64_t wf = __shfl(hw, f);
+    const int64_t sh = ((b >> 6) + f) * 64 + (__ffsll((long long)wf) - 1);
+    jl = (sh - 1) / wslots;
+  } else {
+    jl = (e + wslots >= nnz) ? (nnz - 1) / wslots : ((int64_t)ptr[r + 1] - 1) / wslots;
+  }
   float tot[NCH][VEC];
-  zero(tot);
-  for (int64_t j0 = j + 1 + g; j0 <= jl; j0 += (int64_t)G * BLK) {
-    float blk[NCH][VEC];
-    zero(blk);
-    for (int m = 0; m < BLK; ++m) {
-      const int64_t jj = j0 + (int64_t)m * G;
-      if (jj > jl) break;
-      add_vec<VEC, NCH>(carry + (jj * 2) * kz, nvec, q, LPN, blk);
+  if (jl == j + 1) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) tot[ch][t] = nxt[ch][t];
+  } else {
+    zero(tot);
+    for (int64_t j0 = j + 1 + g; j0 <= jl; j0 += (int64_t)G * BLK) {
+      float blk[NCH][VEC];
+      zero(blk);
+      for (int m = 0; m < BLK; ++m) {
+        const int64_t jj = j0 + (int64_t)m * G;
+        if (jj > jl) break;
+        add_vec<VEC, NCH>(carry + (jj * 2) * kz, nvec, q, LPN, blk);
+      }
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) tot[ch][t] += blk[ch][t];
     }
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
+    for (int m = G / 2; m >= 1; m >>= 1)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) tot[ch][t] += blk[ch][t];
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) tot[ch][t] += __shfl_xor(tot[ch][t], m * LPN);
   }
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1)
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-      for (int t = 0; t < VEC; ++t) tot[ch][t] += __shfl_xor(tot[ch][t], m * LPN);
   if (g == 0) {
-    float res[NCH][VEC];
-    zero(res);
-    add_vec<VEC, NCH>(carry + (j * 2 + 1) * kz, nvec, q, LPN, res);
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) res[ch][t] += tot[ch][t];
-    store_row<VEC, NCH>(Y, r, kz, nvec, q, LPN, res, accumulate);
+      for (int t = 0; t < VEC; ++t) tail[ch][t] += tot[ch][t];
+    store_row<VEC, NCH>(Y, r, kz, nvec, q, LPN, tail, accumulate);
   }
 }
 
