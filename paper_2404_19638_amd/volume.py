@@ -53,11 +53,19 @@ def account(M, N, X, Y, Z, R, C, owned_r, owned_c, comm_r, comm_c, nnz_blk) -> d
     recv_rows = I + J
     msgs = np.zeros((X, Y), np.int64)
     post_rows = np.zeros((X, Y), np.int64)   # SpMM PostComm: partial rows arriving at owners
+    send_rows = np.zeros((X, Y), np.int64)   # PreComm: owned rows sent to the other users
     for x in range(X):
         msgs[x] += (np.asarray(comm_r[x]) > 0).sum(1)
         post_rows[x] += np.asarray(comm_r[x]).sum(0)
+        send_rows[x] += np.asarray(comm_r[x]).sum(0)
     for y in range(Y):
         msgs[:, y] += (np.asarray(comm_c[y]) > 0).sum(1)
+        send_rows[:, y] += np.asarray(comm_c[y]).sum(0)
+    # dense-row memory of the three transports of Section "Sparse communication
+    # model" (rows of K/Z columns): SpC-NB keeps only the rows the block uses;
+    # SpC-RB receives in place but packs what it sends; SpC-BB packs both ways
+    used = R + C
+    mem_nb, mem_rb, mem_bb = used, used + send_rows, used + send_rows + recv_rows
     dense_rows = (M / X) * (Y - 1) / Y + (N / Y) * (X - 1) / X
     P = X * Y * Z
     return dict(
@@ -75,6 +83,11 @@ def account(M, N, X, Y, Z, R, C, owned_r, owned_c, comm_r, comm_c, nnz_blk) -> d
         max_sddmm_reduce_scatter_words=float(np.asarray(nnz_blk).max()) * (Z - 1) / Z,
         max_mem_per_K=float((R + C).max()) / Z,
         dense3d_mem_per_K=(M / X + N / Y) / Z,
+        total_send_rows=int(send_rows.sum()),              # = identity_rows
+        max_send_per_K=float(send_rows.max()) / Z,
+        max_mem_nb_per_K=float(mem_nb.max()) / Z,
+        max_mem_rb_per_K=float(mem_rb.max()) / Z,
+        max_mem_bb_per_K=float(mem_bb.max()) / Z,
     )
 
 

@@ -97,6 +97,9 @@ def test_lambda_and_receive_sets_brute_force(seed):
     total = sum(len(p) - 1 for p in row_parts.values() if p) + \
         sum(len(p) - 1 for p in col_parts.values() if p)
     assert rep["identity_rows"] == total == recv.sum()
+    # every received row is sent once by its owner; buffers only add memory
+    assert rep["total_send_rows"] == total
+    assert rep["max_mem_nb_per_K"] <= rep["max_mem_rb_per_K"] <= rep["max_mem_bb_per_K"]
     # owned counts add up to the used ids; comm rows sum to the receive sets
     for x in range(X):
         assert orr[x]["owned"].sum() == sum(1 for i in range(rb[x], rb[x + 1]) if row_parts[i])
