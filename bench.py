@@ -204,9 +204,10 @@ def main():
     ap.add_argument("--seed", type=int, default=2405)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
-    ap.add_argument("--workload", choices=["share3d", "tiny"], default="share3d",
+    ap.add_argument("--workload", choices=["share3d", "tiny", "precision"], default="share3d",
                     help="share3d: one processor's block of R-MAT 2^24 (the benchmark); "
-                         "tiny: 4096^2 with 40,000 uniform entries, K = 32 (latency-bound)")
+                         "tiny: 4096^2 with 40,000 uniform entries, K = 32 (latency-bound); "
+                         "precision: R-MAT 2^22, degree 32, whole matrix, K = kz = 128")
     ap.add_argument("--row-groups", type=int, default=0, metavar="G",
                     help="owner-grouped local rows (SpC-RB order): seeded keys in [0, G)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -234,7 +235,8 @@ def main():
         torch.cuda.synchronize()
         del a, c
     t0 = time.perf_counter()
-    p = synth.share3d(seed=args.seed) if args.workload == "share3d" else synth.tiny()
+    p = {"share3d": lambda: synth.share3d(seed=args.seed), "tiny": synth.tiny,
+         "precision": synth.precision}[args.workload]()
     log(f"bench: generated {args.workload} block nnz={p.nnz} in {time.perf_counter() - t0:.1f} s")
     rows = torch.from_numpy(p.rows).to(dev)
     cols = torch.from_numpy(p.cols).to(dev)
@@ -343,8 +345,9 @@ def main():
     dominant = max(names, key=lambda n: per_kernel_ms[n])
     achieved = alg[dominant] / (per_kernel_ms[dominant] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    workload = ("rmat24-deg16-block(5,2)-8x8x4-kz32" if args.workload == "share3d"
-                else "uniform-4096x4096-40000nnz-k32")
+    workload = {"share3d": "rmat24-deg16-block(5,2)-8x8x4-kz32",
+                "tiny": "uniform-4096x4096-40000nnz-k32",
+                "precision": "rmat22-deg32-whole-k128"}[args.workload]
     kernels = {n: {"ms": round(per_kernel_ms[n], 5), "alg_bytes": int(alg[n]),
                    "GB_s": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9, 1),
                    "frac_hbm": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -368,7 +371,9 @@ def main():
         "data": "synthetic (seeded R-MAT stand-in for the paper's SuiteSparse graphs)",
         "config": {"workload": workload,
                    **({"rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4", "block": [5, 2]}
-                      if args.workload == "share3d" else {"grid": "1x1x1"}),
+                      if args.workload == "share3d" else
+                      {"rmat_scale": 22, "avg_degree": 32, "grid": "1x1x1"}
+                      if args.workload == "precision" else {"grid": "1x1x1"}),
                    "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
                    "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
                             else "gather A, gather B, SDDMM, SpMM, scatter-reduce"),
