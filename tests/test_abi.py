@@ -95,3 +95,33 @@ def test_variant_check_rules(lib):
     assert f(SPMM, 32, F32, var(4, 0, 0, 1)) == UNSUPPORTED
     # SDDMM ignores the SpMM bits
     assert f(SDDMM, 32, F32, var(4, 0, 0, 1)) == OK
+
+
+def test_host_validation_of_the_widening_entry_points(lib):
+    """Argument checks that return before any device work."""
+    i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    lo_ = lib.spc3d_lambda_owners
+    lo_.argtypes = [i32, vp, vp, i64, i64, vp, vp, vp, vp, vp, vp, sz, vp]
+    assert lo_(0, None, None, 0, 10, None, None, None, None, None, None, 0, None) == 4
+    assert lo_(65, None, None, 0, 10, None, None, None, None, None, None, 0, None) == 4
+    ws = lib.spc3d_lambda_owners_workspace_size
+    ws.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    b = sz()
+    assert ws(5, 5, ctypes.byref(b)) == 1
+    assert ws(0, 100, ctypes.byref(b)) == 0 and b.value >= 800
+    g = lib.spc3d_plan_create_coo_grouped
+    g.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, i64, i64, i64, vp, i32, vp, i32,
+                  ctypes.c_uint32, vp, sz, vp]
+    h = vp()
+    fake = ctypes.c_void_p(16)   # never dereferenced: the count check comes first
+    assert g(ctypes.byref(h), 0, None, None, 0, 10, 0, 10, fake, 0, None, 0, 0, None, 0,
+             None) == 1
+    assert g(ctypes.byref(h), 0, None, None, 0, 10, 0, 10, fake, 5000, None, 0, 0, None, 0,
+             None) == 1
+    c = lib.spc3d_plan_create_csr
+    c.argtypes = [ctypes.POINTER(vp), i64, vp, vp, i64, i64, i64, i64, ctypes.c_uint32, vp, sz,
+                  vp]
+    assert c(ctypes.byref(h), 0, None, None, 0, 10, 0, 10, 0, None, 0, None) == 1
+    go = lib.spc3d_plan_group_offsets
+    go.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i32)]
+    assert go(None, 0, None, None) == 6
