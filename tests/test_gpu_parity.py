@@ -166,6 +166,33 @@ def test_bf16_conversion_over_bit_patterns():
     np.testing.assert_array_equal(_np(got.view(torch.int16)).view(np.uint16), want)
 
 
+def test_bf16_conversion_all_fp32_patterns():
+    """The GPU gather-convert on all 2^32 FP32 bit patterns (16 chunks of 2^28
+    values, generated on the device), bit for bit against the oracle."""
+    spc = _spc()
+    kz = 64
+    n = (1 << 28) // kz
+    ids = torch.arange(n, dtype=torch.int64, device=DEV)
+    plan = spc.plan_create_coo(ids, ids, (0, n), (0, n))
+    out = torch.empty((n, kz), dtype=torch.bfloat16, device=DEV)
+    from concurrent.futures import ThreadPoolExecutor
+
+    def expect(lo, m):   # the oracle on patterns [lo, lo + m), on a host thread
+        return oracle.bf16_rne(np.arange(lo, lo + m, dtype=np.int64).astype(np.uint32)
+                               .view(np.float32))
+
+    part = 1 << 24
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        for c in range(16):
+            base = c << 28
+            want = [ex.submit(expect, base + i, part) for i in range(0, 1 << 28, part)]
+            pats = (torch.arange(1 << 28, dtype=torch.int64, device=DEV) + base).to(torch.int32)
+            spc.gather(plan, spc.ROWS, pats.view(torch.float32).view(n, kz), 0, kz, out=out)
+            got = _np(out.view(torch.int16)).view(np.uint16).ravel()
+            np.testing.assert_array_equal(got, np.concatenate([w.result() for w in want]),
+                                          err_msg=f"chunk {c}")
+
+
 # ------------------------------------------------------------ SDDMM / SpMM
 
 def _local_inputs(p, ref, k0, kz, dtype=np.float32):

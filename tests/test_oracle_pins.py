@@ -193,6 +193,31 @@ def test_bf16_matches_torch_cpu_rounding():
     assert np.isnan(oracle.bf16_to_f32(got[nan])).all()
 
 
+def _bf16_chunk_vs_torch(lo, step):
+    import torch
+    pats = np.arange(lo, lo + step, dtype=np.int64).astype(np.uint32)
+    x = pats.view(np.float32)
+    got = oracle.bf16_rne(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    nan = np.isnan(x)
+    np.testing.assert_array_equal(got[~nan], ref[~nan], err_msg=f"chunk {lo:#x}")
+    g = got[nan]
+    assert ((g & 0x7F80) == 0x7F80).all() and ((g & 0x7F) != 0).all()
+    assert np.array_equal(g >> 15, (pats[nan] >> 31).astype(np.uint16))
+
+
+def test_bf16_all_fp32_patterns_against_torch_cpu():
+    """Every one of the 2^32 FP32 bit patterns: the oracle's rounding equals
+    PyTorch's CPU round-to-nearest-even conversion for all non-NaN inputs;
+    NaNs stay NaNs with their sign.  Chunks run on threads (the oracle's C
+    loop releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    step = 1 << 25
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(_bf16_chunk_vs_torch, lo, step) for lo in range(0, 1 << 32, step)]:
+            f.result()
+
+
 # ------------------------------------------------------------------- SDDMM
 
 def test_sddmm_spmm_hand_example():
