@@ -80,3 +80,37 @@ def test_share3d_step_full_size(share):
     oracle.scatter_add_f32(ref["gmap_r"], p.row_range[0], _np(Y), want, k0)
     spc.scatter_reduce(plan, spc.ROWS, Y, dst, k0)
     np.testing.assert_array_equal(_np(dst).view(np.uint32), want.view(np.uint32))
+
+
+def test_share3d_identities_full_size(share):
+    """Properties that hold at any size, on the full benchmark block:
+    sum_p SDDMM(S, A, B)_p = sum_{l,k} A_loc[l,k] * SpMM(S, B)[l,k] (both sides
+    reduced in FP64 on the GPU, bar 1e-5 of the sum of |terms|), and the
+    transpose symmetry SDDMM(S^T, B, A) = SDDMM(S, A, B) entry by entry,
+    bit-exact (each dot product's reduction order depends on k only)."""
+    from paper_2404_19638_amd import spc3d as spc
+    p, ref = share
+    dev_rows, dev_cols = torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV)
+    plan = spc.plan_create_coo(dev_rows, dev_cols, p.row_range, p.col_range)
+    k0, kz = p.k0, p.kz
+    A = spc.gather(plan, spc.ROWS, torch.from_numpy(p.A_src).to(DEV), k0, kz)
+    B = spc.gather(plan, spc.COLS, torch.from_numpy(p.B_src).to(DEV), k0, kz)
+    vc = torch.from_numpy(p.vals).to(DEV)
+    vals = spc.permute_values(plan, spc.CALLER_TO_SLOT, vc)
+    out, Y = spc.sddmm_spmm(plan, vals, A, B, kz)
+    lhs = out.double().sum()
+    rhs = (A.double() * Y.double()).sum()
+    m = plan.maps()
+    lr = torch.repeat_interleave(torch.arange(plan.R, device=DEV),
+                                 (m["rowptr"][1:] - m["rowptr"][:-1]).long())
+    mag = (vals.double().abs()[:, None] * A.double().abs()[lr]
+           * B.double().abs()[m["colidx"].long()]).sum()
+    _say(f"sum identity: {float(lhs):.6e} vs {float(rhs):.6e} (|terms| {float(mag):.3e})")
+    assert abs(float(lhs - rhs)) <= 1e-5 * float(mag)
+    # transpose symmetry, in caller order
+    planT = spc.plan_create_coo(dev_cols, dev_rows, p.col_range, p.row_range)
+    valsT = spc.permute_values(planT, spc.CALLER_TO_SLOT, vc)
+    outT = spc.sddmm(planT, valsT, B, A, kz)
+    a = spc.permute_values(plan, spc.SLOT_TO_CALLER, spc.sddmm(plan, vals, A, B, kz))
+    b = spc.permute_values(planT, spc.SLOT_TO_CALLER, outT)
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
