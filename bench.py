@@ -204,8 +204,10 @@ def main():
     ap.add_argument("--seed", type=int, default=2405)
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
-    ap.add_argument("--workload", choices=["share3d", "tiny", "precision"], default="share3d",
+    ap.add_argument("--workload", choices=["share3d", "uniform", "tiny", "precision"],
+                    default="share3d",
                     help="share3d: one processor's block of R-MAT 2^24 (the benchmark); "
+                         "uniform: the same block shape with uniform positions; "
                          "tiny: 4096^2 with 40,000 uniform entries, K = 32 (latency-bound); "
                          "precision: R-MAT 2^22, degree 32, whole matrix, K = kz = 128")
     ap.add_argument("--row-groups", type=int, default=0, metavar="G",
@@ -236,7 +238,7 @@ def main():
         del a, c
     t0 = time.perf_counter()
     p = {"share3d": lambda: synth.share3d(seed=args.seed), "tiny": synth.tiny,
-         "precision": synth.precision}[args.workload]()
+         "uniform": synth.share3d_uniform, "precision": synth.precision}[args.workload]()
     log(f"bench: generated {args.workload} block nnz={p.nnz} in {time.perf_counter() - t0:.1f} s")
     rows = torch.from_numpy(p.rows).to(dev)
     cols = torch.from_numpy(p.cols).to(dev)
@@ -346,6 +348,7 @@ def main():
     achieved = alg[dominant] / (per_kernel_ms[dominant] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
     workload = {"share3d": "rmat24-deg16-block(5,2)-8x8x4-kz32",
+                "uniform": "uniform-block(5,2)-8x8x4-kz32-4012517nnz",
                 "tiny": "uniform-4096x4096-40000nnz-k32",
                 "precision": "rmat22-deg32-whole-k128"}[args.workload]
     kernels = {n: {"ms": round(per_kernel_ms[n], 5), "alg_bytes": int(alg[n]),
@@ -372,6 +375,7 @@ def main():
         "config": {"workload": workload,
                    **({"rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4", "block": [5, 2]}
                       if args.workload == "share3d" else
+                      {"grid": "8x8x4", "block": [5, 2]} if args.workload == "uniform" else
                       {"rmat_scale": 22, "avg_degree": 32, "grid": "1x1x1"}
                       if args.workload == "precision" else {"grid": "1x1x1"}),
                    "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,

@@ -15,6 +15,8 @@ Workload recipes
               row ids lie in [5*2^21, 6*2^21) and column ids in
               [2*2^21, 3*2^21).  Dense A and B slabs 2^21 x 128, local K-slice
               z=1 of 4 (k0=32, kz=32).
+``share3d_uniform`` the same block shape, ranges, dense slabs and K-slice
+              with 4,012,517 distinct uniform positions (flat degrees).
 ``precision`` R-MAT on 2^22 vertices, 2^27 samples (average degree 32), the
               whole matrix as one block, K=128.
 ``attention`` R-MAT on 2^20 vertices, 2^25 samples, K=64.
@@ -194,6 +196,24 @@ def share3d(seed: int = 2405, bx: int = 5, by: int = 2, z: int = 1, dense: bool 
     else:
         A = B = None
     return Problem("share3d", rows, cols, vals, rr, cr, A, B, K, z * kz, kz, seed)
+
+
+def share3d_uniform(seed: int = 2410, nnz: int = 4_012_517, bx: int = 5, by: int = 2,
+                    z: int = 1, dense: bool = True) -> Problem:
+    """The 3D-share block's shape (2^21 x 2^21 block (bx, by) of the 8 x 8 grid of
+    2^24 ids, K = 128, K-slice z of 4) with nnz distinct uniform positions."""
+    scale, grid, Z, K = 24, 8, 4, 128
+    span = (1 << scale) // grid
+    rr = (bx * span, (bx + 1) * span)
+    cr = (by * span, (by + 1) * span)
+    rows, cols = uniform_block(span, span, nnz, seed, rr[0], cr[0])
+    vals = uniform_f32(seed + 7, rows.shape[0])
+    kz = K // Z
+    if dense:
+        A, B = _dense_pair(seed, rr, cr, K)
+    else:
+        A = B = None
+    return Problem("share3d_uniform", rows, cols, vals, rr, cr, A, B, K, z * kz, kz, seed)
 
 
 def rmat_whole(scale: int, deg: int, K: int, seed: int, name: str, dense: bool = True) -> Problem:

@@ -1,6 +1,7 @@
 """Parity on the benchmark workload at full size: one processor's 3D share of
 an R-MAT graph (2^24 vertices, average degree 16, block (5,2) of the 8x8
-grid, K-slice z = 1 of 4), run exactly as bench.py's step runs it (gather A,
+grid, K-slice z = 1 of 4), and the same block shape with uniform positions,
+run exactly as bench.py's step runs it (gather A,
 gather B, fused SDDMM+SpMM, scatter-reduce; the library's default shape and
 the variants the selector picks), against the FP64 oracle on every output.
 
@@ -33,9 +34,10 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module")
-def share():
-    p = synth.share3d()
+@pytest.fixture(scope="module", params=["rmat", "uniform"])
+def share(request):
+    """The benchmark block (R-MAT) and its uniform-position counterpart."""
+    p = synth.share3d() if request.param == "rmat" else synth.share3d_uniform()
     ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range)
     return p, ref
 
