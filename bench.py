@@ -202,6 +202,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16 and learned-selector forms")
     ap.add_argument("--seed", type=int, default=2405)
+    ap.add_argument("--graph", action="store_true",
+                    help="time the K steps as replays of one step captured in a HIP graph "
+                         "(both are always measured and reported under 'launch')")
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
     ap.add_argument("--workload", choices=["share3d", "uniform", "tiny", "precision"],
@@ -350,9 +353,28 @@ def main():
                for n, (a, b) in spans.items()}
         return ms, per
 
+    def graph_timed(step, steps, warmup):
+        """Step time from `steps` replays of one step captured in a HIP graph
+        (the same kernels on the same buffers, without per-launch host work)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        del g
+        return ms
+
     b = 4 if args.dtype == "f32" else 2
-    ms_per_step, per_kernel_ms = timed(make_step(args.dtype, args.variant), args.steps,
-                                       args.warmup)
+    main_step = make_step(args.dtype, args.variant)
+    eager_ms, per_kernel_ms = timed(main_step, args.steps, args.warmup)
+    graph_ms = graph_timed(main_step, args.steps, args.warmup)
+    ms_per_step = graph_ms if args.graph else eager_ms
     flops = 4.0 * kz * nnz
     value = flops / (ms_per_step * 1e-3) / 1e9
     alg = algorithmic_bytes(R, C, nnz, kz, b)
@@ -403,6 +425,9 @@ def main():
         "copy_GB_s": round(copy_gbs, 1),
         "step_frac_copy": round(total_alg / (ms_per_step * 1e-3) / 1e9 / copy_gbs, 4),
         "kernels": kernels,
+        "launch": {"timed_steps": "hip graph replays" if args.graph else "eager launches",
+                   "eager_ms_per_step": round(eager_ms, 5),
+                   "graph_ms_per_step": round(graph_ms, 5)},
         "setup_ms": round(setup_ms, 2),
         "setup_warm_ms": round(setup_warm_ms, 3),
         "source_hash": src_hash,
@@ -411,7 +436,7 @@ def main():
         res["cold"] = cold_kernels(make_step(args.dtype, args.variant), names, spans, nev, alg,
                                    args.cold_steps, dev)
     if not args.no_forms:
-        res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_per_step,
+        res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, eager_ms,
                              per_kernel_ms, flops)
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
