@@ -772,10 +772,13 @@ inline int pow2ceil(int n) {
 
 // op: 0 SDDMM, 1 SpMM, 2 fused SDDMM+SpMM.  Defaults (variant -1), from
 // measurements on MI355X: SDDMM on 64-slot work items with lanes covering kz;
-// SpMM and the fused pass (half as many lanes: its batches hold A and B rows)
-// on work items that grow with the block, about nnz / 4096 slots clamped to
-// [64, 512] so that small blocks still launch enough wavefronts, in the
-// windowed family below 2^18 entries and in the group-run family above.
+// SpMM and the fused pass on work items that grow with the block, about
+// nnz / 4096 slots clamped to [64, 512] so that small blocks still launch
+// enough wavefronts, in the windowed family below 2^18 entries and in the
+// group-run family above.  The fused pass holds A and B rows per batch; it
+// takes half as many lanes only for FP32 rows of 16 or more vectors (kz >= 64),
+// where the smaller groups measured faster; narrower rows and bfloat16 keep
+// lanes covering the row.
 inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, int op,
                                int64_t nnz, Shape* sh) {
   const bool spmm = op != 0;
@@ -787,7 +790,7 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
   const int nvec = kz / sh->vec;
   if (variant < 0) {
     sh->lanes = pow2ceil(nvec);
-    if (op == 2) sh->lanes /= 2;
+    if (op == 2 && t == SPC3D_F32 && nvec >= 16) sh->lanes /= 2;
     if (sh->lanes > 16) sh->lanes = 16;
     if (sh->lanes < 2) sh->lanes = 2;
     while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;

@@ -106,6 +106,27 @@ def test_relabel_empty_block():
     A = torch.zeros((0, 8), device=DEV)
     assert spc.sddmm(plan, None, A, A, 8).numel() == 0
     assert spc.spmm(plan, None, A, 0, 8).numel() == 0
+    assert spc.spmm(plan, None, A, 1, 8).numel() == 0
+    out, Y = spc.sddmm_spmm(plan, None, A, A, 8)
+    assert out.numel() == 0 and Y.numel() == 0
+    src = torch.rand((100, 16), device=DEV)
+    assert spc.gather(plan, spc.ROWS, src, 4, 8).numel() == 0
+    assert spc.gather(plan, spc.COLS, src[:10], 8, 8, packed_dtype=torch.bfloat16).numel() == 0
+    dst = src.clone()
+    spc.scatter_reduce(plan, spc.ROWS, A, dst, 4)
+    e = torch.zeros(0, device=DEV)
+    assert spc.permute_values(plan, spc.CALLER_TO_SLOT, e).numel() == 0
+    assert spc.row_softmax(plan, e).numel() == 0
+    assert spc.row_softmax_bwd(plan, e, e).numel() == 0
+    assert spc.row_softmax_apply(plan, e, torch.zeros((0, 2), device=DEV)).numel() == 0
+    assert spc.mul_values(plan, e, e).numel() == 0
+    A16 = torch.zeros((0, 16), device=DEV)   # fused attention covers kz = 16 and up in FP32
+    o, st = spc.attention_fwd(plan, A16, A16, A16)
+    assert o.numel() == 0 and st.numel() == 0
+    f = spc.plan_features(plan, 8, spc.F32)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)          # rows the block does not touch are left unchanged
+    assert torch.isfinite(f).all()
 
 
 def test_relabel_out_of_range_is_an_error():
