@@ -255,40 +255,62 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
   counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Stable scatter: items are visited in rounds of 256 (item r*256 + t of the
-// tile), so the rank of an item among equal digits follows tile order.
+// Stable scatter of one tile of kSortTile keys.  Items are ranked in rounds
+// of 256 (item r*256 + t of the tile), so the rank of an item among equal
+// digits follows tile order.  Each item is first placed in LDS at its
+// position inside the tile's digit-ordered sequence; the tile is then
+// written out in that order, so consecutive threads store consecutive
+// elements of one digit's run instead of one element per cache line.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
     int64_t nblk, const int32_t* __restrict__ offsets, uint64_t* __restrict__ kout,
     int32_t* __restrict__ vout) {
-  __shared__ int base[256];
+  __shared__ uint64_t s_key[kSortTile];
+  __shared__ int32_t s_val[kSortTile];
+  __shared__ int start[256];   // first position of each digit inside the tile
+  __shared__ int cnt[256];     // items of each digit in the tile
+  __shared__ int base[256];    // next free position of each digit (advances per round)
   __shared__ int wcnt[kSortThreads / 64][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  base[t] = offsets[(int64_t)t * nblk + blockIdx.x];
+  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  uint64_t k[kSortRounds];
+  int32_t v[kSortRounds];
+  cnt[t] = 0;
   for (int i = 0; i < kSortThreads / 64; ++i) wcnt[i][t] = 0;
   __syncthreads();
-  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t j = tile + r * kSortThreads + t;
+    k[r] = j < n ? kin[j] : 0;
+    v[r] = j < n ? vin[j] : 0;
+    if (j < n) atomicAdd(&cnt[(int)((k[r] >> shift) & 255)], 1);
+  }
+  __syncthreads();
+  int total;
+  const int st = block_exclusive_sum<kSortThreads>(cnt[t], &total);
+  start[t] = st;
+  base[t] = st;
+  __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t j = tile + r * kSortThreads + t;
     const bool valid = j < n;
-    uint64_t k = valid ? kin[j] : 0;
-    int32_t v = valid ? vin[j] : 0;
-    const int d = (int)((k >> shift) & 255);
+    const int d = (int)((k[r] >> shift) & 255);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < 8; ++bit) {
-      const uint64_t b = __ballot((d >> bit) & 1);
-      peers &= ((d >> bit) & 1) ? b : ~b;
+      const uint64_t bb = __ballot((d >> bit) & 1);
+      peers &= ((d >> bit) & 1) ? bb : ~bb;
     }
     const int rank = __popcll(peers & lt);
     if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
     __syncthreads();
     if (valid) {
-      int off = base[d] + rank;
-      for (int i = 0; i < w; ++i) off += wcnt[i][d];
-      kout[off] = k;
-      vout[off] = v;
+      int pos = base[d] + rank;
+      for (int i = 0; i < w; ++i) pos += wcnt[i][d];
+      s_key[pos] = k[r];
+      s_val[pos] = v[r];
     }
     __syncthreads();
     int add = 0;
@@ -298,6 +320,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     }
     base[t] += add;
     __syncthreads();
+  }
+  // positions [0, total) of the tile now hold its items in (digit, tile order)
+  for (int i = t; i < total; i += kSortThreads) {
+    const uint64_t key = s_key[i];
+    const int d = (int)((key >> shift) & 255);
+    const int within = i - start[d];
+    if (within < 0 || within >= cnt[d]) continue;   // cannot happen; keeps stores in range
+    const int64_t g = (int64_t)offsets[(int64_t)d * nblk + blockIdx.x] + within;
+    if (g < n) {
+      kout[g] = key;
+      vout[g] = s_val[i];
+    }
   }
 }
 
