@@ -88,7 +88,7 @@ __device__ inline bool head_at(const uint64_t* __restrict__ head, int64_t s) {
 // suffix scan over the 64 lanes (shuffles, 6 steps, a fixed order): lane l's
 // tail row continues through the leads of lanes l+1, l+2, ... up to the first
 // lane in which a row starts.
-constexpr int kRun = 8;
+constexpr int kRun = 16;
 
 template <class Op>
 __device__ inline typename Op::St shfl_st(typename Op::St v, int from) {
@@ -278,7 +278,7 @@ __global__ void k_mul_values(int64_t n, const float* __restrict__ a, const float
 
 namespace {
 
-constexpr int kRowItems = 512;   // slots per wavefront work item (kRun per lane)
+constexpr int kRowItems = 64 * kRun;   // slots per wavefront work item (kRun per lane)
 static_assert(kRowItems == 64 * kRun, "one run per lane");
 
 size_t softmax_buffer_bytes(const Plan* p) {
