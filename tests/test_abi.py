@@ -125,3 +125,15 @@ def test_host_validation_of_the_widening_entry_points(lib):
     go = lib.spc3d_plan_group_offsets
     go.argtypes = [vp, ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i32)]
     assert go(None, 0, None, None) == 6
+
+
+def test_c_client_compiles_against_the_header_and_links():
+    """A plain C program (gcc, C11, -Wall -Wextra) includes include/spc3d.h and
+    links libspc3d.so: the boundary needs no C++ and no PyTorch."""
+    import importlib.util
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location(
+        "abi_client_build", os.path.join(here, "abi_client", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert os.path.exists(mod.build())
