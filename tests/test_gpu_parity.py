@@ -275,6 +275,52 @@ def test_sddmm_spmm_parity(name, kz):
         assert_within_mag(_np(fy), o_sp, m_sp, what=f"fused spmm v={v}")
 
 
+@pytest.mark.parametrize("dtype,kz,k0", [("f32", 1024, 0), ("bf16", 1024, 0), ("f32", 255, 3),
+                                         ("f32", 256, 4)])
+def test_largest_row_widths(dtype, kz, k0):
+    """The widest rows the library takes: kz = 1024 with 16-byte vectors (FP32
+    and bfloat16: whole wavefronts per entry) and the scalar path's limit
+    (kz = 255, rows not a multiple of four elements), through SDDMM, SpMM, the
+    transposed SpMM and the fused pass with the default shapes; one past each
+    limit is refused (kz = 256 with vectors as well).  bfloat16 results are
+    held to the FP32 bar against the oracle on the rounded operands
+    (accumulation error only)."""
+    spc = _spc()
+    p = synth.small_rmat(10, 8, 1280, 91, row_range=(0, 1 << 10), col_range=(0, 1 << 10))
+    _say(f"widest rows dtype={dtype} kz={kz} nnz={p.nnz}")
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = _plan(p, spc.BUILD_CSC)
+    A_src, B_src = p.A_src, p.B_src
+    if dtype == "bf16":   # the operands as the GPU sees them after rounding
+        A_src = oracle.bf16_to_f32(oracle.bf16_rne(A_src)).reshape(A_src.shape)
+        B_src = oracle.bf16_to_f32(oracle.bf16_rne(B_src)).reshape(B_src.shape)
+    Aloc, Bloc = _local_inputs_raw(ref, p.row_range, p.col_range, A_src[:, k0:], B_src[:, k0:], kz)
+    o_sd, m_sd = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, A_src,
+                              B_src, k0, kz)
+    o_sd, m_sd = o_sd[ref["perm"]], m_sd[ref["perm"]]
+    o_sp, m_sp = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"],
+                             ref["R"], p.vals, B_src, k0, kz)
+    o_spt, m_spt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"],
+                               ref["C"], p.vals, A_src, k0, kz)
+    tdt = torch.float32 if dtype == "f32" else torch.bfloat16
+    A = torch.from_numpy(np.ascontiguousarray(Aloc)).to(DEV).to(tdt)
+    B = torch.from_numpy(np.ascontiguousarray(Bloc)).to(DEV).to(tdt)
+    vals_slot = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    assert_within_mag(_np(spc.sddmm(plan, vals_slot, A, B, kz)), o_sd, m_sd, what="sddmm")
+    assert_within_mag(_np(spc.spmm(plan, vals_slot, B, 0, kz)), o_sp, m_sp, what="spmm")
+    assert_within_mag(_np(spc.spmm(plan, vals_slot, A, 1, kz)), o_spt, m_spt, what="spmm^T")
+    fo, fy = spc.sddmm_spmm(plan, vals_slot, A, B, kz)
+    assert_within_mag(_np(fo), o_sd, m_sd, what="fused sddmm")
+    assert_within_mag(_np(fy), o_sp, m_sp, what="fused spmm")
+    # one past the limit
+    over = 1025 if kz == 1024 else 257
+    A2 = torch.zeros((plan.R, over), dtype=tdt, device=DEV)
+    B2 = torch.zeros((plan.C, over), dtype=tdt, device=DEV)
+    with pytest.raises(spc.Spc3dError) as ei:
+        spc.sddmm(plan, vals_slot, A2, B2, over)
+    assert ei.value.status in (spc.ERR_INVALID_ARG, spc.ERR_UNSUPPORTED)
+
+
 def _row_pattern(lengths, ncols, seed):
     """COO entries of rows with the given lengths (row i has lengths[i] distinct columns)."""
     rng = np.random.default_rng(seed)
