@@ -38,7 +38,7 @@
  *    local column, caller index).  Values and SDDMM outputs passed to the hot
  *    calls are in this slot order; spc3d_permute_values converts from and to
  *    the caller's COO order.
- *  - Limits: nnz < 2^31; each id range (hi - lo) in [1, 2^31 - 1];
+ *  - Limits: nnz <= 2^31 - 65; each id range (hi - lo) in [1, 2^31 - 2];
  *    kz in [1, 1024] (kz not a multiple of the 16-byte vector width is limited
  *    to 256).
  *  - Distinct plans on distinct streams are independent.  Calls that share a

@@ -614,9 +614,10 @@ spc3d_status validate_ranges(int64_t nnz, int64_t row_lo, int64_t row_hi, int64_
                              int64_t col_hi) {
   if (nnz < 0 || nnz > INT32_MAX - 64)
     return fail(SPC3D_ERR_INVALID_ARG, "nnz=%lld outside [0, 2^31-65]", (long long)nnz);
-  if (row_hi - row_lo < 1 || row_hi - row_lo > INT32_MAX - 1 || col_hi - col_lo < 1 ||
-      col_hi - col_lo > INT32_MAX - 1)
-    return fail(SPC3D_ERR_INVALID_ARG, "id ranges must hold 1..2^31-1 ids");
+  // hi > lo first, so the unsigned difference is the exact width of the range
+  if (row_hi <= row_lo || (uint64_t)row_hi - (uint64_t)row_lo > (uint64_t)INT32_MAX - 1 ||
+      col_hi <= col_lo || (uint64_t)col_hi - (uint64_t)col_lo > (uint64_t)INT32_MAX - 1)
+    return fail(SPC3D_ERR_INVALID_ARG, "id ranges must hold 1..2^31-2 ids");
   return SPC3D_OK;
 }
 

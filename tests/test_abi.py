@@ -137,3 +137,19 @@ def test_c_client_compiles_against_the_header_and_links():
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
     assert os.path.exists(mod.build())
+
+
+def test_size_limits_are_exact_and_overflow_safe():
+    """The documented limits, checked on the host: id ranges of 1..2^31-2 ids,
+    nnz up to 2^31-65; a range with hi <= lo, one id too wide, or spanning the
+    whole int64 line (whose width overflows int64) is refused."""
+    from paper_2404_19638_amd import spc3d as spc
+    n = (1 << 31) - 2
+    assert spc.plan_workspace_size(10, 1 << 40, (1 << 40) + n, 5 << 40, (5 << 40) + n) > 0
+    assert spc.plan_workspace_size((1 << 31) - 65, 0, 10, 0, 10) > 0
+    for args in [(10, 0, n + 1, 0, 10), (10, 0, 10, 7, n + 8), (10, 5, 5, 0, 10),
+                 (10, 0, 10, 9, 3), (10, -(1 << 63), (1 << 63) - 1, 0, 10),
+                 ((1 << 31) - 64, 0, 10, 0, 10), (-1, 0, 10, 0, 10)]:
+        with pytest.raises(spc.Spc3dError) as ei:
+            spc.plan_workspace_size(*args)
+        assert ei.value.status == spc.ERR_INVALID_ARG, args

@@ -129,6 +129,47 @@ def test_relabel_empty_block():
     assert torch.isfinite(f).all()
 
 
+def test_relabel_widest_id_ranges():
+    """Row and column ranges of 2^31 - 2 ids (the limit) far from zero
+    (lo = 2^40 and 5 * 2^40), with entries at both ends of each range: the
+    maps and the CSR arrays equal a brute-force construction (np.unique for
+    globalMap, a lexicographic sort for the slots), localMap is the rank at
+    every used id and -1 elsewhere."""
+    spc = _spc()
+    n = (1 << 31) - 2
+    rlo, clo = 1 << 40, 5 << 40
+    rng = np.random.default_rng(17)
+    r = np.concatenate([[0, 1, n - 1, n - 2, n - 1], rng.integers(0, n, 20000)])
+    c = np.concatenate([[n - 1, 0, 0, n - 1, 5], rng.integers(0, n, 20000)])
+    cell = np.unique(r * (1 << 31) + c)   # distinct positions
+    rows = (cell >> 31) + rlo
+    cols = (cell & ((1 << 31) - 1)) + clo
+    order = rng.permutation(rows.size)   # caller order: shuffled
+    rows, cols = rows[order].astype(np.int64), cols[order].astype(np.int64)
+    _say(f"widest id ranges nnz={rows.size}")
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               (rlo, rlo + n), (clo, clo + n))
+    gr, lr = np.unique(rows, return_inverse=True)
+    gc, lc = np.unique(cols, return_inverse=True)
+    assert (plan.R, plan.C, plan.nnz) == (gr.size, gc.size, rows.size)
+    m = plan.maps()
+    np.testing.assert_array_equal(_np(m["gmap_r"]), gr)
+    np.testing.assert_array_equal(_np(m["gmap_c"]), gc)
+    slot = np.lexsort((np.arange(rows.size), lc, lr))
+    np.testing.assert_array_equal(_np(m["perm"]), slot)
+    np.testing.assert_array_equal(_np(m["colidx"]), lc[slot])
+    np.testing.assert_array_equal(_np(m["rowptr"]),
+                                  np.concatenate([[0], np.cumsum(np.bincount(lr))]))
+    for lmap, g, lo in ((m["lmap_r"], gr, rlo), (m["lmap_c"], gc, clo)):
+        assert lmap.numel() == n
+        at = torch.from_numpy(g - lo).to(DEV)
+        np.testing.assert_array_equal(_np(lmap[at]), np.arange(g.size))
+        assert int((lmap >= 0).sum()) == g.size
+        probe = np.setdiff1d(np.concatenate([np.arange(64), n - 1 - np.arange(64),
+                                             rng.integers(0, n, 4096)]), g - lo)
+        assert (_np(lmap[torch.from_numpy(probe).to(DEV)]) == -1).all()
+
+
 def test_relabel_out_of_range_is_an_error():
     spc = _spc()
     r = torch.tensor([1, 2, 30], dtype=torch.int64, device=DEV)
