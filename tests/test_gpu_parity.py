@@ -362,6 +362,62 @@ def test_largest_row_widths(dtype, kz, k0):
     assert ei.value.status in (spc.ERR_INVALID_ARG, spc.ERR_UNSUPPORTED)
 
 
+def _same_specials(got, ref, mag, what):
+    """NaN exactly where the oracle has NaN, the same signed infinities, and
+    the finite rest within 1e-5 of the magnitude sum."""
+    got = np.asarray(got, np.float64)
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(ref), err_msg=what + " NaN")
+    inf = np.isinf(ref)
+    np.testing.assert_array_equal(np.isinf(got), inf, err_msg=what + " inf")
+    np.testing.assert_array_equal(got[inf], ref[inf], err_msg=what + " inf sign")
+    fin = np.isfinite(ref) & np.isfinite(mag)
+    assert_within_mag(got[fin], ref[fin], mag[fin], what=what)
+    return int(np.isnan(ref).sum()), int(inf.sum())
+
+
+def test_ieee_special_values_propagate():
+    """Every stored entry is computed in IEEE arithmetic, explicit zeros
+    included: an infinite element in an A row, a NaN and an infinity in B
+    rows, and zero values on entries that touch them give the oracle's NaNs
+    (0 * inf, NaN * anything) and signed infinities in SDDMM, SpMM, the
+    transposed SpMM and the fused pass."""
+    spc = _spc()
+    p = _problems()["rmat12"]
+    kz, k0 = 16, 8
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    A_src, B_src, vals = p.A_src.copy(), p.B_src.copy(), p.vals.copy()
+    r0 = int(p.rows[0] - p.row_range[0])
+    c1 = int(p.cols[1] - p.col_range[0])
+    c2 = int(p.cols[2] - p.col_range[0])
+    A_src[r0, k0 + 1] = np.inf
+    B_src[c1, k0 + 3] = np.nan
+    B_src[c2, k0 + 5] = -np.inf
+    touch = (p.rows == p.rows[0]) | (p.cols == p.cols[1]) | (p.cols == p.cols[2])
+    vals[np.flatnonzero(touch)[::2]] = 0.0   # explicit zeros on half of the touching entries
+    vals[3] = 0.0
+    _say(f"ieee specials nnz={p.nnz} touching={int(touch.sum())}")
+    plan = _plan(p, spc.BUILD_CSC)
+    Aloc, Bloc = _local_inputs_raw(ref, p.row_range, p.col_range, A_src[:, k0:], B_src[:, k0:], kz)
+    with np.errstate(invalid="ignore", over="ignore"):
+        o_sd, m_sd = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], vals, A_src,
+                                  B_src, k0, kz)
+        o_sp, m_sp = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"],
+                                 ref["R"], vals, B_src, k0, kz)
+        o_spt, m_spt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"],
+                                   ref["C"], vals, A_src, k0, kz)
+    o_sd, m_sd = o_sd[ref["perm"]], m_sd[ref["perm"]]
+    A = torch.from_numpy(np.ascontiguousarray(Aloc)).to(DEV)
+    B = torch.from_numpy(np.ascontiguousarray(Bloc)).to(DEV)
+    v = torch.from_numpy(vals[ref["perm"]]).to(DEV)
+    nan_sd, inf_sd = _same_specials(_np(spc.sddmm(plan, v, A, B, kz)), o_sd, m_sd, "sddmm")
+    nan_sp, inf_sp = _same_specials(_np(spc.spmm(plan, v, B, 0, kz)), o_sp, m_sp, "spmm")
+    _same_specials(_np(spc.spmm(plan, v, A, 1, kz)), o_spt, m_spt, "spmm^T")
+    fo, fy = spc.sddmm_spmm(plan, v, A, B, kz)
+    _same_specials(_np(fo), o_sd, m_sd, "fused sddmm")
+    _same_specials(_np(fy), o_sp, m_sp, "fused spmm")
+    assert nan_sd > 0 and inf_sd > 0 and nan_sp > 0 and inf_sp > 0   # the case is exercised
+
+
 def _row_pattern(lengths, ncols, seed):
     """COO entries of rows with the given lengths (row i has lengths[i] distinct columns)."""
     rng = np.random.default_rng(seed)
