@@ -91,3 +91,56 @@ def test_step_graph_replays_equal_eager(fused, dtype):
     torch.cuda.synchronize()
     assert torch.equal(Y2.view(torch.int32), Yd.view(torch.int32))
     del g
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_attention_training_step_graph_replays_equal_eager(fused):
+    """Forward and hand-written backward of the graph-attention layer (three
+    kernels, or the fused one-pass forward) captured in one HIP graph: each
+    replay, with eager work between replays, gives the eager step's output and
+    gradients bit for bit.  The backward is seeded with an explicit output
+    gradient, so no reduction kernel of the loss enters the graph."""
+    from paper_2404_19638_amd import spc3d as spc
+    from paper_2404_19638_amd import autograd as ag
+    p = synth.small_rmat(11, 8, 32, 99, row_range=(1 << 10, 1 << 11), col_range=(0, 1 << 10))
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    _say(f"attention graph fused={fused} nnz={plan.nnz}")
+    g = torch.Generator().manual_seed(7)
+    Q = torch.randn((plan.R, 32), generator=g).to(DEV).requires_grad_()
+    Kf = torch.randn((plan.C, 32), generator=g).to(DEV).requires_grad_()
+    V = torch.randn((plan.C, 32), generator=g).to(DEV).requires_grad_()
+    G = torch.randn((plan.R, 32), generator=g).to(DEV)
+
+    def step():
+        for t in (Q, Kf, V):
+            t.grad = None
+        out = ag.gnn_attention(plan, Q, Kf, V, fused=fused)
+        torch.autograd.backward(out, G)
+        return out
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):   # warm-up (buffers, autograd state) off the capture
+        for _ in range(2):
+            out = step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    want = [out.detach().clone()] + [t.grad.clone() for t in (Q, Kf, V)]
+    del out   # drop the warm-up's autograd graph before the capture builds its own
+
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out_s = step()
+    grads_s = [t.grad for t in (Q, Kf, V)]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in [out_s] + grads_s:
+            t.detach().fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        for name, got, ref in zip(("out", "dQ", "dKf", "dV"), [out_s] + grads_s, want):
+            assert torch.equal(got.detach().view(torch.int32), ref.view(torch.int32)), (rep, name)
+        spc.sddmm(plan, None, Q.detach(), Kf.detach())   # eager work between replays
+        torch.cuda.synchronize()
+    del graph
