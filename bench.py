@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16 and learned-selector forms")
     ap.add_argument("--seed", type=int, default=2405)
+    ap.add_argument("--kz", type=int, default=0,
+                    help="K-slice width of the 3D-share blocks (K = 128; Z = K / kz processors "
+                         "along the third grid axis); default 32, i.e. Z = 4")
     ap.add_argument("--graph", action="store_true",
                     help="time the K steps as replays of one step captured in a HIP graph "
                          "(both are always measured and reported under 'launch')")
@@ -250,6 +253,11 @@ def main():
     p = {"share3d": lambda: synth.share3d(seed=args.seed), "tiny": synth.tiny,
          "uniform": synth.share3d_uniform, "precision": synth.precision}[args.workload]()
     log(f"bench: generated {args.workload} block nnz={p.nnz} in {time.perf_counter() - t0:.1f} s")
+    if args.kz:
+        if args.workload not in ("share3d", "uniform") or p.K % args.kz:
+            raise SystemExit("--kz applies to the 3D-share blocks (K = 128) and must divide K")
+        p.kz, p.k0 = args.kz, args.kz * (1 if args.kz < p.K else 0)   # the slice z = 1 (or 0)
+    zdim = p.K // p.kz
     rows = torch.from_numpy(p.rows).to(dev)
     cols = torch.from_numpy(p.cols).to(dev)
     A_src = torch.from_numpy(p.A_src).to(dev)
@@ -388,8 +396,8 @@ def main():
     dominant = max(names, key=lambda n: per_kernel_ms[n])
     achieved = alg[dominant] / (per_kernel_ms[dominant] * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    workload = {"share3d": "rmat24-deg16-block(5,2)-8x8x4-kz32",
-                "uniform": "uniform-block(5,2)-8x8x4-kz32-4012517nnz",
+    workload = {"share3d": f"rmat24-deg16-block(5,2)-8x8x{zdim}-kz{kz}",
+                "uniform": f"uniform-block(5,2)-8x8x{zdim}-kz{kz}-4012517nnz",
                 "tiny": "uniform-4096x4096-40000nnz-k32",
                 "precision": "rmat22-deg32-whole-k128"}[args.workload]
     kernels = {n: {"ms": round(per_kernel_ms[n], 5), "alg_bytes": int(alg[n]),
@@ -414,9 +422,9 @@ def main():
         "dtype": "f32" if args.dtype == "f32" else "bf16-in/f32-acc",
         "data": "synthetic (seeded R-MAT stand-in for the paper's SuiteSparse graphs)",
         "config": {"workload": workload,
-                   **({"rmat_scale": 24, "avg_degree": 16, "grid": "8x8x4", "block": [5, 2]}
+                   **({"rmat_scale": 24, "avg_degree": 16, "grid": f"8x8x{zdim}", "block": [5, 2]}
                       if args.workload == "share3d" else
-                      {"grid": "8x8x4", "block": [5, 2]} if args.workload == "uniform" else
+                      {"grid": f"8x8x{zdim}", "block": [5, 2]} if args.workload == "uniform" else
                       {"rmat_scale": 22, "avg_degree": 32, "grid": "1x1x1"}
                       if args.workload == "precision" else {"grid": "1x1x1"}),
                    "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
