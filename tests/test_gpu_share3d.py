@@ -116,3 +116,36 @@ def test_share3d_identities_full_size(share):
     a = spc.permute_values(plan, spc.SLOT_TO_CALLER, spc.sddmm(plan, vals, A, B, kz))
     b = spc.permute_values(planT, spc.SLOT_TO_CALLER, outT)
     assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+@pytest.mark.parametrize("kz,k0", [(16, 16), (128, 0)])
+def test_share3d_other_kslices(share, kz, k0):
+    """The step at the K-slice widths `bench.py --kz` times (Z = 8 and Z = 1 of
+    the same grid), on the full blocks: packed rows and the scatter-reduce
+    bit-exact, the fused pass's SDDMM and SpMM within 1e-5 of the oracle's
+    magnitude sum on every output."""
+    from paper_2404_19638_amd import spc3d as spc
+    p, ref = share
+    _say(f"share3d kz={kz} nnz={p.nnz}")
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range)
+    A = spc.gather(plan, spc.ROWS, torch.from_numpy(p.A_src).to(DEV), k0, kz)
+    B = spc.gather(plan, spc.COLS, torch.from_numpy(p.B_src).to(DEV), k0, kz)
+    np.testing.assert_array_equal(_np(A), oracle.gather_f32(ref["gmap_r"], p.row_range[0],
+                                                            p.A_src, k0, kz))
+    np.testing.assert_array_equal(_np(B), oracle.gather_f32(ref["gmap_c"], p.col_range[0],
+                                                            p.B_src, k0, kz))
+    vals = spc.permute_values(plan, spc.CALLER_TO_SLOT, torch.from_numpy(p.vals).to(DEV))
+    out, Y = spc.sddmm_spmm(plan, vals, A, B, kz)
+    o_sd, m_sd = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, p.A_src,
+                              p.B_src, k0, kz)
+    assert_within_mag(_np(out), o_sd[ref["perm"]], m_sd[ref["perm"]], what=f"sddmm kz={kz}")
+    del o_sd, m_sd
+    o_sp, m_sp = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"],
+                             ref["R"], p.vals, p.B_src, k0, kz)
+    assert_within_mag(_np(Y), o_sp, m_sp, what=f"spmm kz={kz}")
+    dst = torch.from_numpy(p.A_src).to(DEV)
+    want = p.A_src.copy()
+    oracle.scatter_add_f32(ref["gmap_r"], p.row_range[0], _np(Y), want, k0)
+    spc.scatter_reduce(plan, spc.ROWS, Y, dst, k0)
+    np.testing.assert_array_equal(_np(dst).view(np.uint32), want.view(np.uint32))
