@@ -217,10 +217,11 @@ def main():
                          "(both are always measured and reported under 'launch')")
     ap.add_argument("--fused", type=int, default=1,
                     help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
-    ap.add_argument("--workload", choices=["share3d", "uniform", "tiny", "precision"],
+    ap.add_argument("--workload", choices=["share3d", "uniform", "banded", "tiny", "precision"],
                     default="share3d",
                     help="share3d: one processor's block of R-MAT 2^24 (the benchmark); "
                          "uniform: the same block shape with uniform positions; "
+                         "banded: a diagonal block of the same grid with a banded pattern; "
                          "tiny: 4096^2 with 40,000 uniform entries, K = 32 (latency-bound); "
                          "precision: R-MAT 2^22, degree 32, whole matrix, K = kz = 128")
     ap.add_argument("--row-groups", type=int, default=0, metavar="G",
@@ -251,10 +252,11 @@ def main():
         del a, c
     t0 = time.perf_counter()
     p = {"share3d": lambda: synth.share3d(seed=args.seed), "tiny": synth.tiny,
-         "uniform": synth.share3d_uniform, "precision": synth.precision}[args.workload]()
+         "uniform": synth.share3d_uniform, "banded": synth.share3d_banded,
+         "precision": synth.precision}[args.workload]()
     log(f"bench: generated {args.workload} block nnz={p.nnz} in {time.perf_counter() - t0:.1f} s")
     if args.kz:
-        if args.workload not in ("share3d", "uniform") or p.K % args.kz:
+        if args.workload not in ("share3d", "uniform", "banded") or p.K % args.kz:
             raise SystemExit("--kz applies to the 3D-share blocks (K = 128) and must divide K")
         p.kz, p.k0 = args.kz, args.kz * (1 if args.kz < p.K else 0)   # the slice z = 1 (or 0)
     zdim = p.K // p.kz
@@ -398,6 +400,7 @@ def main():
     src_hash = kernel_source_hash()
     workload = {"share3d": f"rmat24-deg16-block(5,2)-8x8x{zdim}-kz{kz}",
                 "uniform": f"uniform-block(5,2)-8x8x{zdim}-kz{kz}-4012517nnz",
+                "banded": f"banded-hw16384-block(2,2)-8x8x{zdim}-kz{kz}",
                 "tiny": "uniform-4096x4096-40000nnz-k32",
                 "precision": "rmat22-deg32-whole-k128"}[args.workload]
     kernels = {n: {"ms": round(per_kernel_ms[n], 5), "alg_bytes": int(alg[n]),
@@ -425,6 +428,8 @@ def main():
                    **({"rmat_scale": 24, "avg_degree": 16, "grid": f"8x8x{zdim}", "block": [5, 2]}
                       if args.workload == "share3d" else
                       {"grid": f"8x8x{zdim}", "block": [5, 2]} if args.workload == "uniform" else
+                      {"grid": f"8x8x{zdim}", "block": [2, 2], "band_half_width": 16384,
+                       "draws_per_row": 2} if args.workload == "banded" else
                       {"rmat_scale": 22, "avg_degree": 32, "grid": "1x1x1"}
                       if args.workload == "precision" else {"grid": "1x1x1"}),
                    "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,

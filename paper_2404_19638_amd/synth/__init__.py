@@ -142,6 +142,22 @@ def uniform_block(nrows: int, ncols: int, nnz: int, seed: int, row_lo: int = 0, 
     return _take(n, rp, cp)
 
 
+def banded_block(lo: int, n: int, per_row: int, half_width: int, seed: int):
+    """Distinct entries of a banded block over ids [lo, lo + n) on both axes:
+    row i draws per_row columns i + U{-half_width, ..., half_width} (clipped
+    to the range), duplicates dropped, caller order = draw order.  Counter
+    draws (seed, i * per_row + t); the offset is the multiply-shift of the
+    draw's high 32 bits onto 2 * half_width + 1 values."""
+    d = draws_u64(seed, n * per_row)
+    span = np.uint64(2 * half_width + 1)
+    off = (((d >> np.uint64(32)) * span) >> np.uint64(32)).astype(np.int64) - half_width
+    rows = np.repeat(np.arange(n, dtype=np.int64), per_row)
+    cols = np.clip(rows + off, 0, n - 1)
+    _, first = np.unique(rows * n + cols, return_index=True)
+    keep = np.sort(first)
+    return rows[keep] + lo, cols[keep] + lo
+
+
 @dataclass
 class Problem:
     """One local block plus the dense slabs it reads and writes.
@@ -214,6 +230,24 @@ def share3d_uniform(seed: int = 2410, nnz: int = 4_012_517, bx: int = 5, by: int
     else:
         A = B = None
     return Problem("share3d_uniform", rows, cols, vals, rr, cr, A, B, K, z * kz, kz, seed)
+
+
+def share3d_banded(seed: int = 2411, bxy: int = 2, per_row: int = 2, half_width: int = 1 << 14,
+                   z: int = 1, dense: bool = True) -> Problem:
+    """A diagonal block (bxy, bxy) of the 8 x 8 grid over 2^24 ids with a banded
+    pattern (rows reuse nearby columns, as road and mesh graphs in their
+    natural order do); slabs, K = 128 and the K-slice as for share3d."""
+    scale, grid, Z, K = 24, 8, 4, 128
+    span = (1 << scale) // grid
+    rr = (bxy * span, (bxy + 1) * span)
+    rows, cols = banded_block(rr[0], span, per_row, half_width, seed)
+    vals = uniform_f32(seed + 7, rows.shape[0])
+    kz = K // Z
+    if dense:
+        A, B = _dense_pair(seed, rr, rr, K)
+    else:
+        A = B = None
+    return Problem("share3d_banded", rows, cols, vals, rr, rr, A, B, K, z * kz, kz, seed)
 
 
 def rmat_whole(scale: int, deg: int, K: int, seed: int, name: str, dense: bool = True) -> Problem:

@@ -1,9 +1,10 @@
 """Parity on the benchmark workload at full size: one processor's 3D share of
 an R-MAT graph (2^24 vertices, average degree 16, block (5,2) of the 8x8
-grid, K-slice z = 1 of 4), and the same block shape with uniform positions,
-run exactly as bench.py's step runs it (gather A,
-gather B, fused SDDMM+SpMM, scatter-reduce; the library's default shape and
-the variants the selector picks), against the FP64 oracle on every output.
+grid, K-slice z = 1 of 4), the same block shape with uniform positions, and
+a banded diagonal block of the same grid, run exactly as bench.py's step runs
+it (gather A, gather B, fused SDDMM+SpMM, scatter-reduce; the library's
+default shape and the variants the selector picks), against the FP64 oracle
+on every output.
 
 Integer and data-movement results are bit-exact; FP32 results lie within
 1e-5 of the oracle's magnitude sum M elementwise.
@@ -34,10 +35,12 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.fixture(scope="module", params=["rmat", "uniform"])
+@pytest.fixture(scope="module", params=["rmat", "uniform", "banded"])
 def share(request):
-    """The benchmark block (R-MAT) and its uniform-position counterpart."""
-    p = synth.share3d() if request.param == "rmat" else synth.share3d_uniform()
+    """The benchmark block (R-MAT), its uniform-position counterpart, and a
+    banded diagonal block of the same grid."""
+    p = {"rmat": synth.share3d, "uniform": synth.share3d_uniform,
+         "banded": synth.share3d_banded}[request.param]()
     ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range)
     return p, ref
 

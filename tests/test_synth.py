@@ -39,3 +39,18 @@ def test_rmat_block_distinct_in_range_and_skewed():
     assert deg.max() > 8 * deg.mean()          # power-law hubs
     r2, c2 = synth.rmat_block(14, 16 << 14, 77, rr, cr)
     assert np.array_equal(r, r2) and np.array_equal(c, c2)
+
+
+def test_banded_block_distinct_in_band_and_deterministic():
+    lo, n, w = 1000, 5000, 40
+    r1, c1 = synth.banded_block(lo, n, 3, w, 77)
+    r2, c2 = synth.banded_block(lo, n, 3, w, 77)
+    np.testing.assert_array_equal(r1, r2)
+    np.testing.assert_array_equal(c1, c2)
+    assert r1.min() >= lo and r1.max() < lo + n and c1.min() >= lo and c1.max() < lo + n
+    assert np.abs(c1 - r1).max() <= w
+    assert np.unique((r1 - lo) * n + (c1 - lo)).size == r1.size          # distinct
+    assert np.unique(r1).size == n                                       # every row drawn
+    assert r1.size > 0.9 * 3 * n                                         # few duplicates
+    # offsets cover the band on both sides
+    assert (c1 - r1).min() == -w and (c1 - r1).max() == w
