@@ -81,8 +81,9 @@ __device__ inline bool head_at(const uint64_t* __restrict__ head, int64_t s) {
 
 // stats[r] = reduction of row r for rows inside one item; carries for the rest.
 // Each lane owns a run of kRun consecutive slots; the run's head word, its
-// inputs (one 16-byte load per input array where aligned) and the head bit
-// after the item are loaded before any is used.  Rows that start and end in
+// inputs (kRun / 4 16-byte loads per input array where aligned) and the head
+// bit after the item are loaded before any is used.  Runs of 16 measured
+// faster than 8 or 4: half as many wavefronts, more bytes in flight each.  Rows that start and end in
 // a run are written directly; the part of a row before a run's first row
 // start ("lead") and the part after its last ("tail") meet in a segmented
 // suffix scan over the 64 lanes (shuffles, 6 steps, a fixed order): lane l's
