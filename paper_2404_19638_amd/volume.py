@@ -33,6 +33,16 @@ import torch
 from . import spc3d as spc
 
 
+def grid_2d(P: int, Z: int) -> tuple:
+    """X <= Y with X * Y = P / Z and X as close to sqrt(P / Z) as the divisors
+    allow (X = Y when P / Z is a square)."""
+    if P % Z:
+        raise ValueError(f"Z={Z} does not divide P={P}")
+    q = P // Z
+    X = max(d for d in range(1, int(q ** 0.5) + 1) if q % d == 0)
+    return X, q // X
+
+
 def bounds(n: int, parts: int) -> np.ndarray:
     """Equal contiguous ranges: part p covers [b[p], b[p+1])."""
     return np.array([p * n // parts for p in range(parts + 1)], dtype=np.int64)
@@ -155,7 +165,7 @@ def main(argv=None):
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--deg", type=int, default=32)
     ap.add_argument("--P", type=int, default=900)
-    ap.add_argument("--Z", default="1,4,9")
+    ap.add_argument("--Z", default="1,2,4,9")
     ap.add_argument("--seed", type=int, default=2409)
     a = ap.parse_args(argv)
     n = 1 << a.scale
@@ -163,10 +173,8 @@ def main(argv=None):
     rnd_r = synth.draws_u64(a.seed + 1, n)
     rnd_c = synth.draws_u64(a.seed + 2, n)
     for z in (int(v) for v in a.Z.split(",")):
-        q = int(round((a.P / z) ** 0.5))
-        if q * q * z != a.P:
-            raise SystemExit(f"P={a.P} is not q*q*{z}")
-        rep = simulate(rows, cols, n, n, q, q, z, rnd_r, rnd_c)
+        X, Y = grid_2d(a.P, z)
+        rep = simulate(rows, cols, n, n, X, Y, z, rnd_r, rnd_c)
         rep["workload"] = f"rmat{a.scale}-deg{a.deg}"
         print("VOLUME " + json.dumps(rep), flush=True)
 

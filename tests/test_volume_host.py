@@ -134,3 +134,11 @@ def test_no_draws_pick_the_lowest_candidate():
     assert r["owner"].tolist() == [0, -1, 0, 0, 1, -1]
     assert r["owned"].tolist() == [3, 1, 0]
     assert r["comm"].tolist() == [[0, 0, 0], [2, 0, 0], [1, 0, 0]]
+
+
+def test_grid_2d_near_square():
+    from paper_2404_19638_amd.volume import grid_2d
+    assert [grid_2d(900, z) for z in (1, 2, 4, 9)] == [(30, 30), (18, 25), (15, 15), (10, 10)]
+    assert grid_2d(7, 1) == (1, 7)
+    with pytest.raises(ValueError):
+        grid_2d(900, 7)
