@@ -16,6 +16,10 @@ itself one of the library's kernels:
 
 Gradients with respect to A and B of the transposed SpMM need the plan's
 column-major view (SPC3D_BUILD_CSC).
+
+Dense operands may be bfloat16 (the library accumulates in FP32): outputs
+are FP32, an upstream gradient that meets bfloat16 operands in an SDDMM is
+rounded to bfloat16 first, and each returned gradient has its input's type.
 """
 from __future__ import annotations
 
@@ -26,6 +30,13 @@ from . import spc3d as spc
 
 def _needs(ctx, i):
     return ctx.needs_input_grad[i]
+
+
+def _as(grad, like):
+    """A gradient (FP32 from the library) in the type of its input: with
+    bfloat16 operands the products still accumulate in FP32 and only the
+    returned gradient is rounded."""
+    return grad if grad.dtype == like.dtype else grad.to(like.dtype)
 
 
 class SDDMMFn(torch.autograd.Function):
@@ -48,9 +59,9 @@ class SDDMMFn(torch.autograd.Function):
         if ctx.has_vals and _needs(ctx, 1):
             dvals = spc.sddmm(plan, dout, A, B)
         if _needs(ctx, 2):
-            dA = spc.spmm(plan, w, B, transpose=0)
+            dA = _as(spc.spmm(plan, w, B, transpose=0), A)
         if _needs(ctx, 3):
-            dB = spc.spmm(plan, w, A, transpose=1)
+            dB = _as(spc.spmm(plan, w, A, transpose=1), B)
         return None, dvals, dA, dB
 
 
@@ -72,13 +83,15 @@ class SpMMFn(torch.autograd.Function):
         dY = dY.contiguous()
         dvals = dX = None
         if ctx.has_vals and _needs(ctx, 1):
-            # d y_i / d s_p = x_j: one dot per slot
+            # d y_i / d s_p = x_j: one dot per slot (both operands of X's type)
+            dYx = dY.to(X.dtype)
             if ctx.transpose == 0:
-                dvals = spc.sddmm(plan, None, dY, X)
+                dvals = spc.sddmm(plan, None, dYx, X)
             else:
-                dvals = spc.sddmm(plan, None, X, dY)
+                dvals = spc.sddmm(plan, None, X, dYx)
         if _needs(ctx, 2):
-            dX = spc.spmm(plan, vals if ctx.has_vals else None, dY, transpose=1 - ctx.transpose)
+            dX = _as(spc.spmm(plan, vals if ctx.has_vals else None, dY,
+                              transpose=1 - ctx.transpose), X)
         return None, dvals, dX, None
 
 
@@ -150,15 +163,15 @@ class FusedAttentionFn(torch.autograd.Function):
         dout = dout.contiguous()
         e = spc.sddmm(plan, None, Q, Kf)
         alpha = spc.row_softmax_apply(plan, e, stats, out=e)
-        dalpha = spc.sddmm(plan, None, dout, V)
+        dalpha = spc.sddmm(plan, None, dout.to(V.dtype), V)
         de = spc.row_softmax_bwd(plan, alpha, dalpha, out=dalpha)
         dQ = dK = dV = None
         if _needs(ctx, 1):
-            dQ = spc.spmm(plan, de, Kf, transpose=0)
+            dQ = _as(spc.spmm(plan, de, Kf, transpose=0), Q)
         if _needs(ctx, 2):
-            dK = spc.spmm(plan, de, Q, transpose=1)
+            dK = _as(spc.spmm(plan, de, Q, transpose=1), Kf)
         if _needs(ctx, 3):
-            dV = spc.spmm(plan, alpha, dout, transpose=1)
+            dV = _as(spc.spmm(plan, alpha, dout, transpose=1), V)
         return None, dQ, dK, dV
 
 
@@ -183,7 +196,8 @@ def scatter_reduce(plan, axis, packed, dst, k0):
 
 
 def _need_fused(Q, Kf, V):
-    if not spc.attention_supported(Q.shape[1], spc.F32):
+    dt = spc.BF16 if Q.dtype == torch.bfloat16 else spc.F32
+    if not spc.attention_supported(Q.shape[1], dt):
         raise ValueError(f"the fused attention pass does not cover K={Q.shape[1]}")
     if not all(t.data_ptr() % 16 == 0 for t in (Q, Kf, V)):
         raise ValueError("the fused attention pass needs 16-byte aligned Q, Kf and V")

@@ -236,3 +236,39 @@ def test_attention_workload_full_size():
         "forward_ms": round(t_f / reps * 1e3, 3), "backward_ms": round(t_b / reps * 1e3, 3),
         "forward_ms_fused_no_grad": round(t_fused * 1e3, 3),
         "forward_sddmm_spmm_GFLOPs": round(flops / (t_f / reps) / 1e9, 1)}), flush=True)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_bf16_attention_training_against_fp32_on_rounded_inputs(fused):
+    """Graph attention with bfloat16 Q, Kf and V (mixed precision: FP32
+    accumulation, the output gradient rounded to bfloat16 where an SDDMM meets
+    bfloat16 operands, gradients returned in bfloat16).  The forward equals the
+    FP32 layer on the same rounded inputs within 1e-5 of the magnitude of its
+    terms; every gradient is within 2^-6 of the FP32 layer's largest gradient
+    entry (one bfloat16 rounding of dOut and one of the result)."""
+    spc, ag = _mods()
+    p = synth.small_rmat(11, 8, 64, 77, row_range=(1 << 10, 1 << 11), col_range=(0, 1 << 10))
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    g = torch.Generator().manual_seed(11)
+    Qb = torch.randn((plan.R, 32), generator=g).to(DEV).bfloat16()
+    Kb = torch.randn((plan.C, 32), generator=g).to(DEV).bfloat16()
+    Vb = torch.randn((plan.C, 32), generator=g).to(DEV).bfloat16()
+    G = torch.randn((plan.R, 32), generator=g).to(DEV)
+    _say(f"bf16 attention fused={fused} nnz={plan.nnz}")
+    outs, grads = [], []
+    for dt in (torch.bfloat16, torch.float32):
+        ts = [t.to(dt).clone().requires_grad_() for t in (Qb, Kb, Vb)]
+        out = ag.gnn_attention(plan, *ts, fused=fused)
+        torch.autograd.backward(out, G)
+        assert all(t.grad.dtype == dt for t in ts)
+        outs.append(out.detach().float())
+        grads.append([t.grad.float() for t in ts])
+    # forward: the same products of bfloat16 values, accumulated in FP32
+    ref = outs[1]
+    assert (outs[0] - ref).abs().max().item() <= 1e-5 * (ref.abs().max().item() + 1.0)
+    for name, gb, gf in zip(("dQ", "dKf", "dV"), grads[0], grads[1]):
+        bound = 2.0 ** -6 * gf.abs().max().item()
+        err = (gb - gf).abs().max().item()
+        _say(f"  {name}: max |bf16 - fp32| {err:.3e} (bound {bound:.3e})")
+        assert err <= bound, (name, err, bound)
