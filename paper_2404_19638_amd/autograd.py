@@ -18,8 +18,9 @@ Gradients with respect to A and B of the transposed SpMM need the plan's
 column-major view (SPC3D_BUILD_CSC).
 
 Dense operands may be bfloat16 (the library accumulates in FP32): outputs
-are FP32, an upstream gradient that meets bfloat16 operands in an SDDMM is
-rounded to bfloat16 first, and each returned gradient has its input's type.
+are FP32, the upstream gradient of a product with bfloat16 operands is
+rounded to bfloat16 before it enters the backward kernels (half the bytes
+per gathered row), and each returned gradient has its input's type.
 """
 from __future__ import annotations
 
@@ -82,15 +83,15 @@ class SpMMFn(torch.autograd.Function):
         vals, X = ctx.saved_tensors
         dY = dY.contiguous()
         dvals = dX = None
+        dYx = dY.to(X.dtype)   # the upstream gradient in X's type (bfloat16 rows gather half the bytes)
         if ctx.has_vals and _needs(ctx, 1):
-            # d y_i / d s_p = x_j: one dot per slot (both operands of X's type)
-            dYx = dY.to(X.dtype)
+            # d y_i / d s_p = x_j: one dot per slot
             if ctx.transpose == 0:
                 dvals = spc.sddmm(plan, None, dYx, X)
             else:
                 dvals = spc.sddmm(plan, None, X, dYx)
         if _needs(ctx, 2):
-            dX = _as(spc.spmm(plan, vals if ctx.has_vals else None, dY,
+            dX = _as(spc.spmm(plan, vals if ctx.has_vals else None, dYx,
                               transpose=1 - ctx.transpose), X)
         return None, dvals, dX, None
 
@@ -163,7 +164,8 @@ class FusedAttentionFn(torch.autograd.Function):
         dout = dout.contiguous()
         e = spc.sddmm(plan, None, Q, Kf)
         alpha = spc.row_softmax_apply(plan, e, stats, out=e)
-        dalpha = spc.sddmm(plan, None, dout.to(V.dtype), V)
+        dout = dout.to(V.dtype)   # the upstream gradient in the operands' type
+        dalpha = spc.sddmm(plan, None, dout, V)
         de = spc.row_softmax_bwd(plan, alpha, dalpha, out=dalpha)
         dQ = dK = dV = None
         if _needs(ctx, 1):

@@ -229,12 +229,29 @@ def test_attention_workload_full_size():
     assert_within_mag(_np(out)[pick], o, M_out, TOL, "attention out (sampled rows)")
     assert_within_mag(_np(out_fused)[pick], o, M_out, TOL, "fused out (sampled rows)")
     assert_within_mag(_np(tq.grad)[pick], dQ, M_dQ, TOL, "dQ (sampled rows)")
+    # the same layer with bfloat16 Q, Kf, V (mixed precision), timed the same way
+    bq, bk, bv = (t.detach().bfloat16().requires_grad_() for t in (tq, tk, tv))
+    for _ in range(2):
+        (ag.gnn_attention(plan, bq, bk, bv) * tw).sum().backward()
+    torch.cuda.synchronize()
+    b_f = b_b = 0.0
+    for _ in range(reps):
+        bq.grad = bk.grad = bv.grad = None
+        t0 = time.perf_counter()
+        out_b = ag.gnn_attention(plan, bq, bk, bv)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (out_b * tw).sum().backward()
+        torch.cuda.synchronize()
+        b_f += t1 - t0
+        b_b += time.perf_counter() - t1
     flops = 2 * 2 * K * p.nnz
     print("ATTENTION_REPORT " + json.dumps({
         "workload": "rmat20-deg32-whole-K64", "nnz": p.nnz, "R": R, "C": C,
         "forward": "three kernels (SDDMM, row softmax, SpMM)",
         "forward_ms": round(t_f / reps * 1e3, 3), "backward_ms": round(t_b / reps * 1e3, 3),
         "forward_ms_fused_no_grad": round(t_fused * 1e3, 3),
+        "bf16_forward_ms": round(b_f / reps * 1e3, 3), "bf16_backward_ms": round(b_b / reps * 1e3, 3),
         "forward_sddmm_spmm_GFLOPs": round(flops / (t_f / reps) / 1e9, 1)}), flush=True)
 
 
