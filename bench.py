@@ -230,8 +230,9 @@ def main():
                     help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path would shard one "
-                                   "block per GPU of the 3D grid",
+        print(json.dumps({"error": "the benchmark runs on one GPU: spc3d has no exchange "
+                                   "between GPUs (the path would shard one block of the 3D "
+                                   "grid per GPU)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -61,7 +61,7 @@ typedef enum {
   SPC3D_ERR_INVALID_ARG = 1,  /* null pointer, bad size, misalignment, bad enum */
   SPC3D_ERR_OUT_OF_RANGE = 2, /* a global id outside [lo, hi) at plan creation */
   SPC3D_ERR_WORKSPACE = 3,    /* workspace or buffer smaller than required */
-  SPC3D_ERR_UNSUPPORTED = 4,  /* valid request this build does not implement */
+  SPC3D_ERR_UNSUPPORTED = 4,  /* valid request the library does not implement */
   SPC3D_ERR_HIP = 5,          /* a HIP runtime call failed */
   SPC3D_ERR_BAD_HANDLE = 6    /* not a live plan */
 } spc3d_status;
