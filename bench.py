@@ -349,6 +349,8 @@ def main():
     else:
         spans.update(sddmm=(4, 5), spmm=(5, 6), scatter=(6, 7))
 
+    spread = {}   # kernel -> (median, min) ms of the last timed() call
+
     def timed(step, steps, warmup):
         """Step time from exactly `steps` steps with nothing recorded between them
         (the timing markers of the per-kernel pass add gaps between kernels), then
@@ -366,9 +368,11 @@ def main():
         for i in range(steps):
             step(events[i])
         torch.cuda.synchronize()
-        per = {n: float(np.mean([events[i][a].elapsed_time(events[i][b])
-                                 for i in range(steps)]))
-               for n, (a, b) in spans.items()}
+        samples = {n: [events[i][a].elapsed_time(events[i][b]) for i in range(steps)]
+                   for n, (a, b) in spans.items()}
+        per = {n: float(np.mean(v)) for n, v in samples.items()}
+        spread.clear()
+        spread.update({n: (float(np.median(v)), float(np.min(v))) for n, v in samples.items()})
         return ms, per
 
     def graph_timed(step, steps, warmup):
@@ -391,6 +395,7 @@ def main():
     b = 4 if args.dtype == "f32" else 2
     main_step = make_step(args.dtype, args.variant)
     eager_ms, per_kernel_ms = timed(main_step, args.steps, args.warmup)
+    per_kernel_spread = dict(spread)
     graph_ms = graph_timed(main_step, args.steps, args.warmup)
     ms_per_step = graph_ms if args.graph else eager_ms
     flops = 4.0 * kz * nnz
@@ -404,7 +409,9 @@ def main():
                 "banded": f"banded-hw16384-block(2,2)-8x8x{zdim}-kz{kz}",
                 "tiny": "uniform-4096x4096-40000nnz-k32",
                 "precision": "rmat22-deg32-whole-k128"}[args.workload]
-    kernels = {n: {"ms": round(per_kernel_ms[n], 5), "alg_bytes": int(alg[n]),
+    kernels = {n: {"ms": round(per_kernel_ms[n], 5),
+                   "ms_median": round(per_kernel_spread[n][0], 5),
+                   "ms_min": round(per_kernel_spread[n][1], 5), "alg_bytes": int(alg[n]),
                    "GB_s": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9, 1),
                    "frac_hbm": round(alg[n] / (per_kernel_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                for n in names}
