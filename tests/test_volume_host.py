@@ -142,3 +142,21 @@ def test_grid_2d_near_square():
     assert grid_2d(7, 1) == (1, 7)
     with pytest.raises(ValueError):
         grid_2d(900, 7)
+
+
+def test_dense_pattern_non_square_grid():
+    """X != Y (the paper's Z = 2 at P = 900 needs one): with every cell stored
+    and owners spread evenly, every processor receives exactly
+    (M/X)(Y-1)/Y + (N/Y)(X-1)/X rows per slice, the Dense3D volume."""
+    M, N = 120, 240   # block ranges divisible by the parts: owners split exactly evenly
+    for X, Y, Z in ((2, 3, 1), (3, 5, 2), (4, 6, 1)):
+        cells = np.arange(M * N, dtype=np.int64)
+        rows, cols = cells // N, cells % N
+        rnd_r = np.array([((i % Y) * 2 ** 64 + 2 ** 63) // Y for i in range(M)], np.uint64)
+        rnd_c = np.array([((j % X) * 2 ** 64 + 2 ** 63) // X for j in range(N)], np.uint64)
+        rep, _, _, _ = _oracle_dist3d(rows, cols, M, N, X, Y, Z, rnd_r, rnd_c)
+        want = ((M / X) * (Y - 1) / Y + (N / Y) * (X - 1) / X) / Z
+        assert rep["dense3d_recv_per_K"] == pytest.approx(want)
+        assert rep["max_recv_per_K"] == pytest.approx(want)
+        assert rep["mean_recv_per_K"] == pytest.approx(want)
+        assert rep["dense3d_formula_per_K"] is None
