@@ -234,6 +234,22 @@ def test_sddmm_spmm_hand_example():
     assert out.sum() == g["sum_identity"]
 
 
+def test_magnitude_sums_hand_example():
+    """The magnitude sums M that every floating-point bar scales with: the
+    hand-worked values (entry p1 of the SDDMM and row 15 of the SpMM cancel,
+    so a magnitude taken as |value| fails here)."""
+    g = _hand()
+    A = np.array(g["A_src"], np.float32)
+    B = np.array(g["B_src"], np.float32)
+    vals = np.array(g["vals"], np.float32)
+    _, mag = oracle.sddmm(g["rows"], g["cols"], 10, 20, vals, A, B, g["k0"], g["kz"])
+    np.testing.assert_array_equal(mag, g["sddmm_mag"])
+    lm = oracle.relabel(g["rows"], g["cols"], g["row_range"], g["col_range"])
+    _, ymag = oracle.spmm(g["rows"], g["cols"], 10, 20, lm["lmap_r"], lm["R"], vals, B, g["k0"],
+                          g["kz"])
+    np.testing.assert_array_equal(ymag, g["spmm_mag"])
+
+
 def _tiny_problem(seed, M=37, N=29, K=6, nnz=200, lo=(3, 50)):
     rng = np.random.default_rng(seed)
     flat = rng.choice(M * N, nnz, replace=False)
@@ -252,6 +268,17 @@ def test_sddmm_dense_masked_brute_force():
     want = vals.astype(np.float64) * dense[rows - rr[0], cols - cr[0]]
     np.testing.assert_allclose(out, want, rtol=0, atol=1e-15)
     assert (mag >= np.abs(out) - 1e-15).all()
+    # M_p = |s_p| * sum_k |a_k b_k| over the slice only: the dense product of
+    # the absolute values, sampled by the mask (each FP32 product is exact in
+    # FP64, so only the order of four additions differs)
+    absdense = (np.abs(A[:, 1:5].astype(np.float64)) @ np.abs(B[:, 1:5].astype(np.float64)).T)
+    want_mag = np.abs(vals.astype(np.float64)) * absdense[rows - rr[0], cols - cr[0]]
+    np.testing.assert_allclose(mag, want_mag, rtol=1e-15, atol=0)
+    # the pin is sharp: with these signs |dot| < sum |a b| for most entries,
+    # and the full-K sum differs from the slice's
+    assert (np.abs(out) < mag * (1 - 1e-6)).mean() > 0.5
+    full = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)).T
+    assert not np.allclose(mag, np.abs(vals) * full[rows - rr[0], cols - cr[0]])
 
 
 def test_sddmm_identity_pattern_is_diagonal():
@@ -286,6 +313,10 @@ def test_spmm_dense_brute_force():
     dense = S @ B[:, 2:5].astype(np.float64)                               # library GEMM
     np.testing.assert_allclose(Y, dense[lm["gmap_r"] - rr[0]], rtol=0, atol=1e-14)
     assert (mag + 1e-15 >= np.abs(Y)).all()
+    # M[l][k] = sum_p |s_p b_k|: |S| |B| over the slice, at the local rows
+    absdense = np.abs(S) @ np.abs(B[:, 2:5].astype(np.float64))
+    np.testing.assert_allclose(mag, absdense[lm["gmap_r"] - rr[0]], rtol=1e-14, atol=0)
+    assert (np.abs(Y) < mag * (1 - 1e-6)).mean() > 0.5
 
 
 def test_spmm_permutation_pattern_returns_rows_exactly():
