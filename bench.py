@@ -73,6 +73,18 @@ def load_traffic(kernel: str, workload: str, src_hash: str):
     return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or 'unknown'."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, budget_s=12.0):
     """The FP64 oracle (as it stands, single-threaded) on the same workload."""
     import numpy as np
@@ -98,7 +110,7 @@ def cpu_baseline(p, budget_s=12.0):
     t_step = t_total / reps
     flops = 4.0 * kz * p.nnz
     return {"value": round(flops / t_step / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": (f"the full workload: {reps} oracle steps (gather A, gather B, SDDMM, SpMM, "
                        f"scatter-reduce in FP64, one thread) on the same block, "
                        f"{t_step * 1e3:.1f} ms per step; oracle localization {t_setup:.2f} s")}

@@ -201,7 +201,9 @@ spc3d_status spc3d_sddmm(spc3d_plan plan, const float* d_vals, const void* d_A, 
                          spc3d_dtype ab_t, int32_t kz, float* d_out, int mode, int variant,
                          hipStream_t stream);
 
-/* Bytes of scratch spc3d_spmm needs for (transpose, kz, variant). */
+/* Bytes of scratch spc3d_spmm and spc3d_sddmm_spmm need for (transpose, kz,
+ * variant): enough for either operand type, aligned or not, fused or not.
+ * Errors: INVALID_ARG or UNSUPPORTED when no shape of `variant` fits kz. */
 spc3d_status spc3d_spmm_buffer_size(spc3d_plan plan, int transpose, int32_t kz, int variant,
                                     size_t* bytes);
 

@@ -46,9 +46,13 @@ class SDDMMFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, plan, vals, A, B):
         ctx.plan = plan
+        # the kernels take packed operands: a sliced input (e.g. a column block
+        # of a wider tensor) is copied once and the copy serves both passes
+        vals = None if vals is None else vals.contiguous()
+        A, B = A.contiguous(), B.contiguous()
         ctx.save_for_backward(vals if vals is not None else torch.empty(0), A, B)
         ctx.has_vals = vals is not None
-        return spc.sddmm(plan, vals, A.contiguous(), B.contiguous())
+        return spc.sddmm(plan, vals, A, B)
 
     @staticmethod
     def backward(ctx, dout):
@@ -74,8 +78,10 @@ class SpMMFn(torch.autograd.Function):
         ctx.plan = plan
         ctx.transpose = transpose
         ctx.has_vals = vals is not None
+        vals = None if vals is None else vals.contiguous()
+        X = X.contiguous()
         ctx.save_for_backward(vals if vals is not None else torch.empty(0), X)
-        return spc.spmm(plan, vals, X.contiguous(), transpose=transpose)
+        return spc.spmm(plan, vals, X, transpose=transpose)
 
     @staticmethod
     def backward(ctx, dY):

@@ -446,7 +446,8 @@ spc3d_status spc3d_attention_fwd(spc3d_plan h, const void* d_Q, const void* d_K,
   const size_t need = (size_t)nitems * 2 * (size_t)(kz + 4) * 4;
   if (buf_bytes < need)
     return fail(SPC3D_ERR_WORKSPACE, "attention buffer %zu bytes < %zu required", buf_bytes, need);
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   float* carry = static_cast<float*>(d_buf);
   if (t == SPC3D_F32)

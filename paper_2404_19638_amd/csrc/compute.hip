@@ -32,7 +32,8 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
                 (size_t)nitems * 2 * (size_t)kz * 4);
   const size_t lds = sh.window ? 0 : 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec, fused);
   if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   const int64_t nblocks = (nitems + 3) / 4;
   const Orient o = transpose ? p->csc() : p->csr();
@@ -81,7 +82,8 @@ spc3d_status spc3d_sddmm(spc3d_plan h, const float* d_vals, const void* d_A, con
   Shape sh;
   st = pick_shape(kz, ab_t, aligned16(d_A) && aligned16(d_B), variant, 0, p->nnz, &sh);
   if (st != SPC3D_OK) return st;
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
   const int64_t nblocks = (nitems + 3) / 4;
@@ -113,15 +115,27 @@ spc3d_status spc3d_spmm_buffer_size(spc3d_plan h, int transpose, int32_t kz, int
   if (st != SPC3D_OK) return st;
   if (!bytes) return fail(SPC3D_ERR_INVALID_ARG, "bytes is NULL");
   if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
-  Shape sh;
-  // The buffer does not depend on the element type or alignment.
-  st = pick_shape(kz, SPC3D_F32, true, variant, 1, p->nnz, &sh);
-  if (st != SPC3D_OK && variant >= 0) {
-    st = pick_shape(kz, SPC3D_F32, false, variant, 1, p->nnz, &sh);
-    if (st != SPC3D_OK) return st;
-  }
-  const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
-  *bytes = (size_t)(nitems > 0 ? nitems : 1) * 2 * (size_t)kz * 4;
+  // The work-item size, and so the number of carries, depends on the shape a
+  // call takes: the operand type, whether the operands are 16-byte aligned
+  // and whether the pass is fused.  The size covers every shape that can run.
+  int64_t items = 0;
+  bool any = false;
+  spc3d_status first = SPC3D_OK;
+  for (int op = 1; op <= 2; ++op)
+    for (int t = 0; t < 2; ++t)
+      for (int al = 1; al >= 0; --al) {
+        Shape sh;
+        st = pick_shape(kz, t ? SPC3D_BF16 : SPC3D_F32, al != 0, variant, op, p->nnz, &sh);
+        if (st == SPC3D_OK) {
+          any = true;
+          const int64_t n = (p->nnz + sh.items - 1) / sh.items;
+          items = n > items ? n : items;
+        } else if (first == SPC3D_OK) {
+          first = st;
+        }
+      }
+  if (!any) return first;
+  *bytes = (size_t)(items > 0 ? items : 1) * 2 * (size_t)kz * 4;
   return SPC3D_OK;
 }
 

@@ -73,8 +73,21 @@ spc3d_status fail(spc3d_status s, const char* fmt, ...);
 spc3d_status hip_fail(hipError_t e, const char* what);
 // Resolves a handle to a live plan (BAD_HANDLE otherwise).
 spc3d_status get_plan(spc3d_plan h, Plan** out);
-// Makes the plan's device current for the calling thread.
-spc3d_status use_device(const Plan* p);
+// Makes the plan's device current for the calling thread until the guard
+// goes out of scope, then gives the thread back the device it had.
+class DeviceGuard {
+ public:
+  DeviceGuard() = default;
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+  spc3d_status enter(const Plan* p);
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1;   // the caller's device when enter() switched away from it
+};
 
 #define SPC3D_HIP(call)                                  \
   do {                                                   \

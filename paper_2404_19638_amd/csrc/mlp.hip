@@ -249,7 +249,8 @@ spc3d_status spc3d_plan_features(spc3d_plan h, int transpose, int32_t kz, spc3d_
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 8-byte aligned");
   if (buf_bytes < SPC3D_FEATURES_BUFFER_BYTES)
     return fail(SPC3D_ERR_WORKSPACE, "features buffer needs %d bytes", SPC3D_FEATURES_BUFFER_BYTES);
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   unsigned long long* hist = static_cast<unsigned long long*>(d_buf);
   int* mx = reinterpret_cast<int*>(hist + kBins);

@@ -181,7 +181,8 @@ spc3d_status spc3d_gather(spc3d_plan h, spc3d_axis axis, const void* d_src, spc3
   const int64_t n = axis == SPC3D_ROWS ? p->R : p->C;
   if (n == 0) return SPC3D_OK;
   if (!d_src || !d_packed) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   const int64_t* gmap = axis == SPC3D_ROWS ? p->gmap_r : p->gmap_c;
   const int64_t lo = axis == SPC3D_ROWS ? p->row_lo : p->col_lo;
@@ -232,7 +233,8 @@ spc3d_status spc3d_scatter_reduce(spc3d_plan h, spc3d_axis axis, const float* d_
   const int64_t n = axis == SPC3D_ROWS ? p->R : p->C;
   if (n == 0) return SPC3D_OK;
   if (!d_packed || !d_dst) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   const int64_t* gmap = axis == SPC3D_ROWS ? p->gmap_r : p->gmap_c;
   const int64_t lo = axis == SPC3D_ROWS ? p->row_lo : p->col_lo;

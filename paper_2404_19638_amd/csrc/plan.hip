@@ -52,10 +52,13 @@ spc3d_status get_plan(spc3d_plan h, Plan** out) {
   return SPC3D_OK;
 }
 
-spc3d_status use_device(const Plan* p) {
+spc3d_status DeviceGuard::enter(const Plan* p) {
   int cur = -1;
   SPC3D_HIP(hipGetDevice(&cur));
-  if (cur != p->device) SPC3D_HIP(hipSetDevice(p->device));
+  if (cur != p->device) {
+    SPC3D_HIP(hipSetDevice(p->device));
+    prev_ = cur;
+  }
   return SPC3D_OK;
 }
 
@@ -901,7 +904,8 @@ spc3d_status spc3d_permute_values(spc3d_plan h, int direction, const float* d_in
   if (p->nnz == 0) return SPC3D_OK;
   if (!d_in || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL array");
   if (d_in == d_out) return fail(SPC3D_ERR_INVALID_ARG, "in and out alias");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   hipLaunchKernelGGL(k_permute, dim3(grid_for(p->nnz, 256)), dim3(256), 0, stream, p->nnz,
                      p->perm, direction, d_in, d_out);

@@ -354,7 +354,8 @@ spc3d_status spc3d_row_softmax(spc3d_plan h, const float* d_e, float* d_alpha, v
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
   if (buf_bytes < softmax_buffer_bytes(p))
     return fail(SPC3D_ERR_WORKSPACE, "softmax buffer too small");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   SoftmaxStat::St* stats;
   st = row_reduce<SoftmaxStat>(p, d_e, nullptr, d_buf, stream, &stats);
@@ -378,7 +379,8 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan h, const float* d_alpha, const flo
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
   if (buf_bytes < softmax_buffer_bytes(p))
     return fail(SPC3D_ERR_WORKSPACE, "softmax buffer too small");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   DotSum::St* stats;
   st = row_reduce<DotSum>(p, d_alpha, d_dalpha, d_buf, stream, &stats);
@@ -398,7 +400,8 @@ spc3d_status spc3d_row_softmax_apply(spc3d_plan h, const float* d_e, const float
   if (!d_e || !d_stats || !d_alpha) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_stats) & 7u)
     return fail(SPC3D_ERR_INVALID_ARG, "stats must be 8-byte aligned");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   hipLaunchKernelGGL(k_softmax_apply, dim3(apply_blocks(p->nnz)), dim3(256), 0, stream, p->nnz,
                      p->head, p->tile_row, reinterpret_cast<const SoftmaxStat::St*>(d_stats), d_e,
@@ -414,7 +417,8 @@ spc3d_status spc3d_mul_values(spc3d_plan h, const float* d_a, const float* d_b, 
   if (st != SPC3D_OK) return st;
   if (p->nnz == 0) return SPC3D_OK;
   if (!d_a || !d_b || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
-  st = use_device(p);
+  DeviceGuard dg;
+  st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   hipLaunchKernelGGL(k_mul_values, dim3(blocks_for(p->nnz)), dim3(256), 0, stream, p->nnz, d_a,
                      d_b, d_out);
