@@ -62,6 +62,26 @@ def _attention_magnitudes(rowptr, colidx, Q, Kf, V, alpha, dout, de):
     return M_out, M_dQ, M_dK, M_dV
 
 
+def _attention_magnitudes_sparse(rowptr, colidx, Q, Kf, V, alpha, dout, de, chunk=1 << 20):
+    """_attention_magnitudes for millions of entries: the per-entry bound of
+    |dalpha_p| in chunks, the row and column sums as sparse products."""
+    import scipy.sparse as sps
+    R, C = Q.shape[0], Kf.shape[0]
+    nnz = colidx.shape[0]
+    lr = np.repeat(np.arange(R, dtype=np.int64), np.diff(rowptr))
+    aW, aV = np.abs(dout), np.abs(V)
+    dal = np.empty(nnz)
+    for s in range(0, nnz, chunk):
+        t = min(s + chunk, nnz)
+        dal[s:t] = np.einsum("ij,ij->i", aW[lr[s:t]], aV[colidx[s:t]])
+    rowsum = np.bincount(lr, alpha * dal, minlength=R)
+    dem = alpha * (dal + rowsum[lr]) + np.abs(de)
+    del dal, rowsum, lr
+    S_a = sps.csr_matrix((alpha, colidx, rowptr), shape=(R, C))
+    S_d = sps.csr_matrix((dem, colidx, rowptr), shape=(R, C))
+    return (S_a @ aV, S_d @ np.abs(Kf), (S_d.T @ np.abs(Q)), (S_a.T @ aW))
+
+
 @pytest.mark.parametrize("K,fused", [(8, False), (16, True)])
 def test_attention_backward_fd_instance(K, fused):
     """K = 8: the three-kernel layer; K = 16: the fused forward, whose backward
@@ -159,20 +179,10 @@ def test_sddmm_spmm_gather_gradients_with_values():
     assert_within_mag(gB[ref["gmap_c"] - lo_c, k0:k0 + kz], yb1 + yb2, mb1 + mb2, TOL, "dB_src")
 
 
-def _rows_subset(rowptr, colidx, rows_pick):
-    """CSR of the picked rows (all their entries) with compacted column ids."""
-    starts, ends = rowptr[rows_pick], rowptr[rows_pick + 1]
-    cnt = ends - starts
-    sub_ptr = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
-    idx = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)])
-    cols = colidx[idx]
-    ucols, inv = np.unique(cols, return_inverse=True)
-    return sub_ptr, inv.astype(np.int32), ucols, idx
-
-
 def test_attention_workload_full_size():
-    """R-MAT 2^20, degree 32, K = 64: forward + backward on the GPU, sampled rows
-    of the output and of dQ against the oracle, forward/backward timings."""
+    """R-MAT 2^20, degree 32, K = 64: forward + backward on the GPU, the output
+    (three-kernel and fused forward), dQ, dKf and dV compared with the FP64
+    oracle element by element at full size, forward/backward timings."""
     spc, ag = _mods()
     p = synth.attention(dense=False)
     K = 64
@@ -217,18 +227,25 @@ def test_attention_workload_full_size():
             tq.grad = tk.grad = tv.grad = None
     m = plan.maps()
     rowptr, colidx = _np(m["rowptr"]), _np(m["colidx"])
-    rng = np.random.default_rng(3)
-    pick = np.sort(rng.choice(R, size=500, replace=False))
-    sub_ptr, sub_col, ucols, _ = _rows_subset(rowptr, colidx, pick)
-    Qd = Q[pick].astype(np.float64)
-    Kd, Vd = Kf[ucols].astype(np.float64), V[ucols].astype(np.float64)
-    Wd = W[pick].astype(np.float64)
-    e, alpha, o = oracle.attention_fwd(sub_ptr, sub_col, Qd, Kd, Vd)
-    de, dQ, _, _ = oracle.attention_bwd(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd)
-    M_out, M_dQ, _, _ = _attention_magnitudes(sub_ptr, sub_col, Qd, Kd, Vd, alpha, Wd, de)
-    assert_within_mag(_np(out)[pick], o, M_out, TOL, "attention out (sampled rows)")
-    assert_within_mag(_np(out_fused)[pick], o, M_out, TOL, "fused out (sampled rows)")
-    assert_within_mag(_np(tq.grad)[pick], dQ, M_dQ, TOL, "dQ (sampled rows)")
+    got = {"out": _np(out), "fused out": _np(out_fused), "dQ": _np(tq.grad),
+           "dKf": _np(tk.grad), "dV": _np(tv.grad)}
+    # every row and column, the longest included (about 64,500 entries each),
+    # against the FP64 oracle at full size (tens of seconds on one host core)
+    _say("attention workload: FP64 oracle forward and backward at full size")
+    Qd, Kd, Vd, Wd = (x.astype(np.float64) for x in (Q, Kf, V, W))
+    e, alpha, o = oracle.attention_fwd(rowptr, colidx, Qd, Kd, Vd)
+    de, dQ, dK, dV = oracle.attention_bwd(rowptr, colidx, Qd, Kd, Vd, alpha, Wd)
+    del e
+    M_out, M_dQ, M_dK, M_dV = _attention_magnitudes_sparse(rowptr, colidx, Qd, Kd, Vd, alpha,
+                                                           Wd, de)
+    lens_r, lens_c = np.diff(rowptr), np.bincount(colidx, minlength=C)
+    _say(f"  longest row {lens_r.max()}, longest column {lens_c.max()}")
+    assert_within_mag(got["out"], o, M_out, TOL, "attention out (full size)")
+    assert_within_mag(got["fused out"], o, M_out, TOL, "fused out (full size)")
+    assert_within_mag(got["dQ"], dQ, M_dQ, TOL, "dQ (full size)")
+    assert_within_mag(got["dKf"], dK, M_dK, TOL, "dKf (full size)")
+    assert_within_mag(got["dV"], dV, M_dV, TOL, "dV (full size)")
+    del Qd, Kd, Vd, Wd, alpha, o, de, dQ, dK, dV, M_out, M_dQ, M_dK, M_dV, got
     # the same layer with bfloat16 Q, Kf, V (mixed precision), timed the same way
     bq, bk, bv = (t.detach().bfloat16().requires_grad_() for t in (tq, tk, tv))
     for _ in range(2):
@@ -259,10 +276,13 @@ def test_attention_workload_full_size():
 def test_bf16_attention_training_against_fp32_on_rounded_inputs(fused):
     """Graph attention with bfloat16 Q, Kf and V (mixed precision: FP32
     accumulation, the output gradient rounded to bfloat16 where an SDDMM meets
-    bfloat16 operands, gradients returned in bfloat16).  The forward equals the
-    FP32 layer on the same rounded inputs within 1e-5 of the magnitude of its
-    terms; every gradient is within 2^-6 of the FP32 layer's largest gradient
-    entry (one bfloat16 rounding of dOut and one of the result)."""
+    bfloat16 operands, gradients returned in bfloat16).  Against the FP64
+    oracle on the rounded inputs (and rounded output gradient): the forward
+    within 2e-5 M, every gradient within 2e-5 M plus one bfloat16 rounding.
+    Beside it, against the FP32 layer on the same inputs: the forward within
+    1e-5 of the magnitude of its terms, every gradient within 2^-6 of the FP32
+    layer's largest gradient entry (one bfloat16 rounding of dOut and one of
+    the result)."""
     spc, ag = _mods()
     p = synth.small_rmat(11, 8, 64, 77, row_range=(1 << 10, 1 << 11), col_range=(0, 1 << 10))
     plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
@@ -289,3 +309,22 @@ def test_bf16_attention_training_against_fp32_on_rounded_inputs(fused):
         err = (gb - gf).abs().max().item()
         _say(f"  {name}: max |bf16 - fp32| {err:.3e} (bound {bound:.3e})")
         assert err <= bound, (name, err, bound)
+    # Against the FP64 oracle on the same rounded values: Q, Kf, V as stored in
+    # bfloat16 and the output gradient rounded to bfloat16 as the backward
+    # rounds it before its SDDMM and transposed SpMM.  The forward (FP32 out)
+    # meets the FP32 bar; each returned gradient is that bar plus its own
+    # rounding to bfloat16 (unit roundoff 2^-8).
+    m = plan.maps()
+    rowptr, colidx = _np(m["rowptr"]), _np(m["colidx"])
+    Qd, Kd, Vd = (t.float().cpu().numpy().astype(np.float64) for t in (Qb, Kb, Vb))
+    Gd = G.bfloat16().float().cpu().numpy().astype(np.float64)
+    _, alpha, o = oracle.attention_fwd(rowptr, colidx, Qd, Kd, Vd)
+    de, dQ, dK, dV = oracle.attention_bwd(rowptr, colidx, Qd, Kd, Vd, alpha, Gd)
+    Ms = _attention_magnitudes(rowptr, colidx, Qd, Kd, Vd, alpha, Gd, de)
+    assert_within_mag(_np(outs[0]), o, Ms[0], TOL, "bf16 attention out vs oracle")
+    for name, gb, want, M in zip(("dQ", "dKf", "dV"), grads[0], (dQ, dK, dV), Ms[1:]):
+        gb = _np(gb).astype(np.float64)
+        bound = TOL * M + 2.0 ** -8 * (np.abs(want) + TOL * M) + 1e-37
+        err = np.abs(gb - want)
+        _say(f"  {name} vs oracle: max err/bound {float((err / bound).max()):.3f}")
+        assert (err <= bound).all(), (name, int((err > bound).sum()))

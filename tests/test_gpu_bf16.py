@@ -79,10 +79,12 @@ def test_bf16_paths_against_both_references(kz):
             assert_within_mag(_np(YT), yt, myt, rel, f"spmm^T {tag} v={v}")
 
 
-def _sample_rows_oracle(p, rng, ns, Bsrc, k0, kz, lo_c):
-    """Oracle SpMM rows for ns sampled global rows (compact local ids)."""
-    rows_g = np.unique(p.rows)
-    pick = np.sort(rng.choice(rows_g, size=min(ns, rows_g.size), replace=False))
+def _sample_rows_oracle(p, rng, ns, Bsrc, k0, kz, lo_c, longest=64):
+    """Oracle SpMM rows for ns sampled global rows plus the `longest` rows
+    with the most entries (compact local ids)."""
+    rows_g, counts = np.unique(p.rows, return_counts=True)
+    top = rows_g[np.argsort(counts, kind="stable")[-longest:]]
+    pick = np.union1d(rng.choice(rows_g, size=min(ns, rows_g.size), replace=False), top)
     sel = np.isin(p.rows, pick)
     rr = p.row_range
     lmap = np.full(rr[1] - rr[0], -1, np.int32)
@@ -94,7 +96,8 @@ def _sample_rows_oracle(p, rng, ns, Bsrc, k0, kz, lo_c):
 
 def test_precision_workload_full_size():
     """R-MAT 2^22, degree 32, K=128 as one block: relabel invariants at full size,
-    FP32 and BF16 SDDMM / SpMM on sampled outputs against the FP64 oracle."""
+    FP32 and BF16 SDDMM / SpMM on sampled outputs against the FP64 oracle (the
+    SpMM sample holds 2,000 random rows and the 64 longest, up to 163K entries)."""
     spc = _spc()
     p = synth.precision()
     K = p.K
@@ -145,6 +148,10 @@ def test_precision_workload_full_size():
             assert_within_mag(_np(out_s)[sample], o, mo, rel, f"{name} sddmm(sep) vs {tag}")
             report[f"{name}_sddmm_vs_{tag}"] = error_report(got, o, mo)
             pick, y, my = _sample_rows_oracle(p, np.random.default_rng(11), 2000, Bref, 0, K, 0)
+            if tag == "fp32_inputs" and name == "f32":
+                _say(f"  sampled rows include rows of up to "
+                     f"{int(np.bincount(np.searchsorted(pick, p.rows[np.isin(p.rows, pick)])).max())}"
+                     f" entries")
             loc = _np(m["lmap_r"])[pick - p.row_range[0]]
             gy = _np(Y[torch.from_numpy(loc).long().to(DEV)])
             assert_within_mag(gy, y, my, rel, f"{name} spmm vs {tag}")

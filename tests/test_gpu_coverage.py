@@ -1,0 +1,326 @@
+"""GPU parity on the paths that only long rows, accumulation and scalar
+shapes reach, each output compared element by element with the FP64 oracle.
+
+* Rows and columns of 2^17 to 3*10^5 entries among short ones (Eq. (2) holds
+  for every row, however long): the SpMM splits such a row over hundreds of
+  work items and its carry fix-up adds their partial sums in several rounds
+  of G*16 items.  Plain, transposed and fused calls, FP32 and bfloat16, the
+  default shape and every SpMM family (group runs, 16-row batches, windowed;
+  work items of 64 to 512 slots).
+* ACCUMULATE of the fused pass (SDDMM values and SpMM rows: the Z-partial
+  sums of the PostComm phase) and of the transposed SpMM.
+* bfloat16 operands whose rows are not whole 16-byte vectors (kz = 4, 12, 20)
+  or whose buffers are not 16-byte aligned: the scalar gather and compute
+  paths.  An FP32 operand off 16-byte alignment with a buffer sized by
+  spc3d_spmm_buffer_size.
+
+Bars: |x - x*| <= 1e-5 M (M the oracle's magnitude sum) for FP32 results and
+for bfloat16 operands against the oracle on the same rounded inputs; a
+result added into a prefilled output carries one more FP32 rounding,
+|x - (x0 + x*)| <= 1e-5 M + 2^-23 (|x0| + M).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_19638_amd import synth
+from helpers import assert_within_mag
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():   # pragma: no cover
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="no GPU")]
+
+DEV = "cuda:0"
+U32 = 2.0 ** -23   # two units of FP32 roundoff: one rounding of an added result
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _spc():
+    from paper_2404_19638_amd import spc3d
+    return spc3d
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _bf16_tensor(u16):
+    """bfloat16 device tensor holding the given bit patterns."""
+    return torch.from_numpy(np.ascontiguousarray(u16).view(np.int16)).to(DEV).view(torch.bfloat16)
+
+
+def _bf16_round(x):
+    return oracle.bf16_to_f32(oracle.bf16_rne(x))
+
+
+def _assert_accumulated(got, pre, ref, mag, what):
+    got = np.asarray(got, np.float64)
+    pre = np.asarray(pre, np.float64)
+    bound = 1e-5 * mag + U32 * (np.abs(pre) + mag) + 1e-37
+    err = np.abs(got - (pre + ref))
+    bad = err > bound
+    assert not bad.any(), (what, int(bad.sum()), float(err[bad].max()))
+
+
+# ------------------------------------------------ rows of 2^17+ entries
+
+N_HUB = 1 << 19
+HUB_ROW_LEN = (2 ** 17 + 123, 2 ** 18 - 17, 300_001)
+HUB_COL_LEN = (2 ** 17 + 45, 2 ** 18 + 3)
+HUB_RANGES = ((3 * N_HUB, 4 * N_HUB), (N_HUB, 2 * N_HUB))
+
+
+def _hub_block(seed=91):
+    """Distinct entries of a 2^19 x 2^19 block (global ids offset from zero):
+    three rows and two columns of HUB_*_LEN entries at seeded positions among
+    150,000 uniform entries; caller order shuffled."""
+    n = N_HUB
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for r, L in zip(rng.choice(n, len(HUB_ROW_LEN), replace=False), HUB_ROW_LEN):
+        rows.append(np.full(L, r, np.int64))
+        cols.append(rng.choice(n, L, replace=False).astype(np.int64))
+    for c, L in zip(rng.choice(n, len(HUB_COL_LEN), replace=False), HUB_COL_LEN):
+        cols.append(np.full(L, c, np.int64))
+        rows.append(rng.choice(n, L, replace=False).astype(np.int64))
+    rows.append(rng.integers(0, n, 150_000))
+    cols.append(rng.integers(0, n, 150_000))
+    r, c = np.concatenate(rows), np.concatenate(cols)
+    _, first = np.unique(r * n + c, return_index=True)
+    sel = np.sort(first)[rng.permutation(first.size)]
+    (rlo, _), (clo, _) = HUB_RANGES
+    return r[sel] + rlo, c[sel] + clo
+
+
+# (lg lanes, lg items[, wide[, window]]) per (dtype, kz): the group-run family
+# with 8- and 16-row batches and the windowed family, 64- to 512-slot items.
+HUB_VARIANTS = {
+    ("f32", 32): [(2, 3), (3, 3, 1), (1, 0, 0, 1), (3, 3, 0, 1)],
+    ("f32", 128): [(4, 3), (3, 3), (5, 2), (4, 3, 1), (3, 3, 0, 1)],
+    ("bf16", 32): [(1, 2), (2, 3, 1), (2, 0, 0, 1), (1, 2, 0, 1)],
+    ("bf16", 128): [(2, 3), (3, 3, 1), (4, 2), (3, 3, 0, 1)],
+}
+
+
+def _fixup_rounds(length, lg_lanes, lg_items):
+    """Rounds of the carry fix-up's loop for a row of `length` slots: the row
+    spans about length / W work items, G = 64 / lanes groups add 16 each."""
+    W, G = 64 << lg_items, 64 >> lg_lanes
+    return -(-(length // W) // (G * 16))
+
+
+@pytest.mark.parametrize("dt,kz", sorted(HUB_VARIANTS))
+def test_long_rows_and_columns_every_family(dt, kz):
+    spc = _spc()
+    rows, cols = _hub_block()
+    rr, cr = HUB_RANGES
+    nnz = rows.size
+    _say(f"hub block {dt} kz={kz} nnz={nnz}")
+    vals = synth.uniform_f32(92, nnz)
+    A_src = synth.dense_f32(93, 0, N_HUB, kz)
+    B_src = synth.dense_f32(94, 0, N_HUB, kz)
+    ref = oracle.relabel(rows, cols, rr, cr, csc=True)
+    lens_r = np.diff(ref["rowptr"])
+    lens_c = np.diff(ref["colptr"])
+    assert lens_r.max() >= HUB_ROW_LEN[-1] and lens_c.max() >= HUB_COL_LEN[-1]
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               rr, cr, spc.BUILD_CSC)
+    m = plan.maps()
+    for k in ("rowptr", "colidx", "perm", "colptr", "slot_t"):
+        np.testing.assert_array_equal(_np(m[k]), ref[k], err_msg=k)
+    Aloc = oracle.gather_f32(ref["gmap_r"], rr[0], A_src, 0, kz)
+    Bloc = oracle.gather_f32(ref["gmap_c"], cr[0], B_src, 0, kz)
+    if dt == "bf16":
+        A = _bf16_tensor(oracle.bf16_rne(Aloc))
+        B = _bf16_tensor(oracle.bf16_rne(Bloc))
+        A_ref, B_ref = _bf16_round(A_src), _bf16_round(B_src)
+        code = spc.BF16
+    else:
+        A = torch.from_numpy(Aloc).to(DEV)
+        B = torch.from_numpy(Bloc).to(DEV)
+        A_ref, B_ref = A_src, B_src
+        code = spc.F32
+    del A_src, B_src
+    v = torch.from_numpy(vals[ref["perm"]]).to(DEV)
+    o_sd, m_sd = oracle.sddmm(rows, cols, rr[0], cr[0], vals, A_ref, B_ref, 0, kz)
+    o_sd, m_sd = o_sd[ref["perm"]], m_sd[ref["perm"]]
+    y, my = oracle.spmm(rows, cols, rr[0], cr[0], ref["lmap_r"], ref["R"], vals, B_ref, 0, kz)
+    yt, myt = oracle.spmm(cols, rows, cr[0], rr[0], ref["lmap_c"], ref["C"], vals, A_ref, 0, kz)
+    del A_ref, B_ref
+
+    assert_within_mag(_np(spc.sddmm(plan, v, A, B, kz)), o_sd, m_sd, what=f"sddmm {dt} kz={kz}")
+    rounds = []
+    for var in [-1] + HUB_VARIANTS[(dt, kz)]:
+        vv = var if isinstance(var, int) else spc.variant(*var)
+        _say(f"  variant {var}")
+        for op in (spc.OP_SPMM, spc.OP_SDDMM_SPMM):
+            assert spc.variant_check(op, kz, code, vv) == spc.OK, (var, op)
+        if not isinstance(var, int):
+            rounds.append((_fixup_rounds(int(lens_r.max()), var[0], var[1]),
+                           _fixup_rounds(int(lens_c.max()), var[0], var[1])))
+        assert_within_mag(_np(spc.spmm(plan, v, B, 0, kz, variant=vv)), y, my,
+                          what=f"spmm {dt} kz={kz} v={var}")
+        assert_within_mag(_np(spc.spmm(plan, v, A, 1, kz, variant=vv)), yt, myt,
+                          what=f"spmm^T {dt} kz={kz} v={var}")
+        fo, fy = spc.sddmm_spmm(plan, v, A, B, kz, variant=vv)
+        assert_within_mag(_np(fo), o_sd, m_sd, what=f"fused sddmm {dt} kz={kz} v={var}")
+        assert_within_mag(_np(fy), y, my, what=f"fused spmm {dt} kz={kz} v={var}")
+        del fo, fy
+    # every explicit shape runs the fix-up's loop at least twice on the longest row
+    assert all(r >= 2 for r, _ in rounds) and all(c >= 2 for _, c in rounds), rounds
+
+    # ACCUMULATE: the fused pass adds into prefilled out and Y, the transposed
+    # SpMM into a prefilled Y^T (default shape)
+    out0 = synth.uniform_f32(95, nnz)
+    Y0 = synth.uniform_f32(96, plan.R * kz).reshape(plan.R, kz)
+    YT0 = synth.uniform_f32(97, plan.C * kz).reshape(plan.C, kz)
+    fo = torch.from_numpy(out0).to(DEV)
+    fy = torch.from_numpy(Y0).to(DEV)
+    spc.sddmm_spmm(plan, v, A, B, kz, out=fo, Y=fy, mode=spc.ACCUMULATE)
+    _assert_accumulated(_np(fo), out0, o_sd, m_sd, "fused sddmm ACCUMULATE")
+    _assert_accumulated(_np(fy), Y0, y, my, "fused spmm ACCUMULATE")
+    yt_acc = torch.from_numpy(YT0).to(DEV)
+    spc.spmm(plan, v, A, 1, kz, out=yt_acc, mode=spc.ACCUMULATE)
+    _assert_accumulated(_np(yt_acc), YT0, yt, myt, "spmm^T ACCUMULATE")
+
+
+# ------------------------------------------- accumulation on a small block
+
+@pytest.mark.parametrize("variant", [-1, (3, 3), (3, 0, 0, 1)])
+def test_accumulate_fused_and_transposed_small(variant):
+    """Two K-slices added in order into the same out / Y / Y^T give the oracle's
+    full-K result; each addition within the accumulated bar."""
+    spc = _spc()
+    p = synth.small_rmat(12, 8, 64, 51, row_range=(1 << 11, 1 << 12), col_range=(0, 1 << 11))
+    kz = 32
+    vv = variant if isinstance(variant, int) else spc.variant(*variant)
+    _say(f"accumulate small nnz={p.nnz} variant={variant}")
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    v = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    Asrc = torch.from_numpy(p.A_src).to(DEV)
+    Bsrc = torch.from_numpy(p.B_src).to(DEV)
+    out = torch.zeros(plan.nnz, device=DEV)
+    Y = torch.zeros((plan.R, kz), device=DEV)
+    YT = torch.zeros((plan.C, kz), device=DEV)
+    for z, k0 in enumerate((0, kz)):
+        A = spc.gather(plan, spc.ROWS, Asrc, k0, kz)
+        B = spc.gather(plan, spc.COLS, Bsrc, k0, kz)
+        before = (_np(out), _np(Y), _np(YT))
+        spc.sddmm_spmm(plan, v, A, B, kz, out=out, Y=Y, mode=spc.ACCUMULATE, variant=vv)
+        spc.spmm(plan, v, A, 1, kz, out=YT, mode=spc.ACCUMULATE, variant=vv)
+        o, mo = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, p.A_src,
+                             p.B_src, k0, kz)
+        y, my = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"],
+                            ref["R"], p.vals, p.B_src, k0, kz)
+        yt, myt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"],
+                              ref["C"], p.vals, p.A_src, k0, kz)
+        _assert_accumulated(_np(out), before[0], o[ref["perm"]], mo[ref["perm"]], f"out z={z}")
+        _assert_accumulated(_np(Y), before[1], y, my, f"Y z={z}")
+        _assert_accumulated(_np(YT), before[2], yt, myt, f"Y^T z={z}")
+
+
+# ------------------------------------------------------- scalar shapes
+
+def _bf16_scalar_case(spc, p, ref, plan, kz, k0, misalign):
+    """Gathers (FP32 -> bfloat16 and bfloat16 -> bfloat16) and every compute
+    call with bfloat16 packed operands; misalign puts A 2 bytes off 16-byte
+    alignment."""
+    R, C = plan.R, plan.C
+    Asrc = torch.from_numpy(p.A_src).to(DEV)
+    Bsrc = torch.from_numpy(p.B_src).to(DEV)
+    if misalign:
+        abuf = torch.empty(R * kz + 8, dtype=torch.bfloat16, device=DEV)
+        A = abuf[1:1 + R * kz].view(R, kz)
+        assert A.data_ptr() % 16 != 0 and A.is_contiguous()
+    else:
+        A = torch.empty((R, kz), dtype=torch.bfloat16, device=DEV)
+    spc.gather(plan, spc.ROWS, Asrc, k0, kz, out=A)
+    B = spc.gather(plan, spc.COLS, Bsrc, k0, kz, torch.bfloat16)
+    want_A = oracle.gather_bf16(ref["gmap_r"], p.row_range[0], p.A_src, k0, kz)
+    want_B = oracle.gather_bf16(ref["gmap_c"], p.col_range[0], p.B_src, k0, kz)
+    np.testing.assert_array_equal(_np(A.view(torch.int16)).view(np.uint16), want_A)
+    np.testing.assert_array_equal(_np(B.view(torch.int16)).view(np.uint16), want_B)
+    # bfloat16 source, bfloat16 packing: a bit copy
+    Bsrc16 = _bf16_tensor(oracle.bf16_rne(p.B_src))
+    B2 = spc.gather(plan, spc.COLS, Bsrc16, k0, kz, torch.bfloat16)
+    np.testing.assert_array_equal(_np(B2.view(torch.int16)).view(np.uint16), want_B)
+
+    Ar, Br = _bf16_round(p.A_src), _bf16_round(p.B_src)
+    v = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    o, mo = oracle.sddmm(p.rows, p.cols, p.row_range[0], p.col_range[0], p.vals, Ar, Br, k0, kz)
+    o, mo = o[ref["perm"]], mo[ref["perm"]]
+    y, my = oracle.spmm(p.rows, p.cols, p.row_range[0], p.col_range[0], ref["lmap_r"], ref["R"],
+                        p.vals, Br, k0, kz)
+    yt, myt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"], ref["C"],
+                          p.vals, Ar, k0, kz)
+    tag = f"bf16 kz={kz} misalign={misalign}"
+    assert_within_mag(_np(spc.sddmm(plan, v, A, B, kz)), o, mo, what=f"sddmm {tag}")
+    assert_within_mag(_np(spc.spmm(plan, v, B, 0, kz)), y, my, what=f"spmm {tag}")
+    assert_within_mag(_np(spc.spmm(plan, v, A, 1, kz)), yt, myt, what=f"spmm^T {tag}")
+    fo, fy = spc.sddmm_spmm(plan, v, A, B, kz)
+    assert_within_mag(_np(fo), o, mo, what=f"fused sddmm {tag}")
+    assert_within_mag(_np(fy), y, my, what=f"fused spmm {tag}")
+
+
+@pytest.mark.parametrize("kz,misalign", [(4, False), (12, False), (20, False), (16, True),
+                                         (20, True)])
+def test_bf16_scalar_paths(kz, misalign):
+    spc = _spc()
+    p = synth.small_rmat(12, 8, 32, 52, row_range=(1 << 11, 1 << 12), col_range=(0, 1 << 11))
+    k0 = 32 - kz - 3   # an odd column offset: no 16-byte source vectors either
+    _say(f"bf16 scalar kz={kz} misalign={misalign} nnz={p.nnz}")
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    _bf16_scalar_case(spc, p, ref, plan, kz, k0, misalign)
+
+
+def test_fp32_misaligned_operand_with_sized_buffer():
+    """FP32 kz = 8 on a block of 300,000 entries: a misaligned X takes the
+    scalar shape, whose work items are smaller than the aligned shape's; the
+    buffer sized by spc3d_spmm_buffer_size must serve both (plain, transposed
+    and fused calls)."""
+    spc = _spc()
+    n, nnz, kz = 1 << 16, 300_000, 8
+    rows, cols = synth.uniform_block(n, n, nnz, 53, row_lo=n, col_lo=0)
+    rr, cr = (n, 2 * n), (0, n)
+    vals = synth.uniform_f32(54, nnz)
+    A_src = synth.dense_f32(55, 0, n, kz)
+    B_src = synth.dense_f32(56, 0, n, kz)
+    _say(f"fp32 misaligned kz={kz} nnz={nnz}")
+    ref = oracle.relabel(rows, cols, rr, cr, csc=True)
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               rr, cr, spc.BUILD_CSC)
+    R, C = plan.R, plan.C
+    Aloc = oracle.gather_f32(ref["gmap_r"], rr[0], A_src, 0, kz)
+    Bloc = oracle.gather_f32(ref["gmap_c"], cr[0], B_src, 0, kz)
+    abuf = torch.empty(R * kz + 4, device=DEV)
+    bbuf = torch.empty(C * kz + 4, device=DEV)
+    A = abuf[1:1 + R * kz].view(R, kz)
+    B = bbuf[1:1 + C * kz].view(C, kz)
+    A.copy_(torch.from_numpy(Aloc))
+    B.copy_(torch.from_numpy(Bloc))
+    assert A.data_ptr() % 16 and B.data_ptr() % 16
+    v = torch.from_numpy(vals[ref["perm"]]).to(DEV)
+    o, mo = oracle.sddmm(rows, cols, rr[0], cr[0], vals, A_src, B_src, 0, kz)
+    o, mo = o[ref["perm"]], mo[ref["perm"]]
+    y, my = oracle.spmm(rows, cols, rr[0], cr[0], ref["lmap_r"], ref["R"], vals, B_src, 0, kz)
+    yt, myt = oracle.spmm(cols, rows, cr[0], rr[0], ref["lmap_c"], ref["C"], vals, A_src, 0, kz)
+    for t in (0, 1):
+        need = spc.spmm_buffer_size(plan, t, kz)
+        buf = torch.empty(need, dtype=torch.uint8, device=DEV)
+        X, want, wm = (B, y, my) if t == 0 else (A, yt, myt)
+        assert_within_mag(_np(spc.spmm(plan, v, X, t, kz, buf=buf)), want, wm,
+                          what=f"misaligned spmm transpose={t}")
+    buf = torch.empty(spc.spmm_buffer_size(plan, 0, kz), dtype=torch.uint8, device=DEV)
+    fo, fy = spc.sddmm_spmm(plan, v, A, B, kz, buf=buf)
+    assert_within_mag(_np(fo), o, mo, what="misaligned fused sddmm")
+    assert_within_mag(_np(fy), y, my, what="misaligned fused spmm")
