@@ -235,6 +235,27 @@ spc3d_status spc3d_sddmm_spmm(spc3d_plan plan, const float* d_vals, const void* 
                               float* d_Y, int mode, int variant, void* d_buf, size_t buf_bytes,
                               hipStream_t stream);
 
+/* Bytes of the library's static scratch array (one per GPU) that
+ * spc3d_sddmm_spmm_static uses in place of a caller buffer. */
+#define SPC3D_STATIC_SCRATCH_BYTES (8u << 20)
+
+/* spc3d_sddmm_spmm for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and results, with the SpMM carries kept in a device
+ * array of SPC3D_STATIC_SCRATCH_BYTES that the library holds on each GPU it
+ * runs on until the process ends, so no scratch argument is taken and nothing
+ * is allocated or freed.  The caller still owns the inputs and outputs.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and must be ordered by the caller.  A call whose
+ * carries need more than SPC3D_STATIC_SCRATCH_BYTES (2 * kz * 4 bytes per
+ * work item; e.g. 8 MiB covers 4M entries at kz = 128 in the default shape)
+ * returns SPC3D_ERR_WORKSPACE before any launch.  Other errors as for
+ * spc3d_sddmm_spmm. */
+spc3d_status spc3d_sddmm_spmm_static(spc3d_plan plan, const float* d_vals, const void* d_A,
+                                     const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
+                                     float* d_Y, int mode, int variant, hipStream_t stream);
+
 /* PostComm, local side: SpC-BB unpacking with reduction at the owner (paper:
  * "Building SpMM with SpComm3D", partial A rows sent to their owners):
  *   d_dst[(gmap[l] - lo)*ld_dst + k0 + k] += d_packed[l*kz + k]   (IEEE FP32)

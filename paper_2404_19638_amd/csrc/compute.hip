@@ -1,6 +1,8 @@
 // SDDMM / SpMM entry points: argument checks, variant choice and launch.
 // The kernels and their design notes are in kernels.h; their instantiations
 // are spread over inst_*.hip so they compile in parallel.
+#include <mutex>
+
 #include "kernels.h"
 
 namespace spc3d {
@@ -17,19 +19,26 @@ SPC3D_EXTERN_LAUNCHERS(bf16_t, 1)
 
 namespace {
 
-// Shared body of spc3d_spmm and spc3d_sddmm_spmm.
+// Shared body of spc3d_spmm, spc3d_sddmm_spmm and spc3d_sddmm_spmm_static
+// (static_buf: d_buf is the library's own scratch array).
 spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d_X,
                       spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant, void* d_buf,
-                      size_t buf_bytes, hipStream_t stream, const void* d_A, float* d_out) {
+                      size_t buf_bytes, hipStream_t stream, const void* d_A, float* d_out,
+                      bool static_buf = false) {
   const bool fused = d_A != nullptr;
   Shape sh;
   const bool al = aligned16(d_X) && aligned16(d_Y) && (!fused || aligned16(d_A));
   spc3d_status st = pick_shape(kz, x_t, al, variant, fused ? 2 : 1, p->nnz, &sh);
   if (st != SPC3D_OK) return st;
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
-  if (buf_bytes < (size_t)nitems * 2 * (size_t)kz * 4)
-    return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes,
-                (size_t)nitems * 2 * (size_t)kz * 4);
+  const size_t need = (size_t)nitems * 2 * (size_t)kz * 4;
+  if (buf_bytes < need) {
+    if (static_buf)
+      return fail(SPC3D_ERR_WORKSPACE,
+                  "this call needs %zu bytes of scratch; the library's static scratch holds %zu "
+                  "(use spc3d_sddmm_spmm with a caller buffer)", need, buf_bytes);
+    return fail(SPC3D_ERR_WORKSPACE, "SpMM buffer %zu bytes < %zu required", buf_bytes, need);
+  }
   const size_t lds = sh.window ? 0 : 4 * spmm_wave_lds(sh.items, sh.lanes, sh.nch, sh.vec, fused);
   if (lds > 65536) return fail(SPC3D_ERR_UNSUPPORTED, "variant needs %zu bytes of LDS", lds);
   DeviceGuard dg;
@@ -57,6 +66,45 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   }
 #undef SPC3D_RUN
   SPC3D_LAUNCHED(fused ? "sddmm_spmm" : "spmm");
+  return SPC3D_OK;
+}
+
+// Arguments common to spc3d_sddmm_spmm and spc3d_sddmm_spmm_static.
+spc3d_status check_fused_args(spc3d_plan h, Plan** p, spc3d_dtype ab_t, int32_t kz, int mode) {
+  spc3d_status st = get_plan(h, p);
+  if (st != SPC3D_OK) return st;
+  if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
+  if (mode != SPC3D_OVERWRITE && mode != SPC3D_ACCUMULATE)
+    return fail(SPC3D_ERR_INVALID_ARG, "bad mode");
+  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
+  return SPC3D_OK;
+}
+
+// The scratch of spc3d_sddmm_spmm_static: the SpMM carries of one call, in a
+// device array the library owns.  Each GPU the library runs on holds its own
+// copy (kept until the process ends); host code reaches it only through the
+// device address hipGetSymbolAddress gives with that GPU current.
+static __device__ __align__(256) char scratch[SPC3D_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+spc3d_status static_scratch(void** out) {
+  int dev = -1;
+  SPC3D_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(SPC3D_ERR_UNSUPPORTED, "device %d beyond the %d the static scratch serves", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* addr = nullptr;
+    SPC3D_HIP(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)));
+    if (!addr) return fail(SPC3D_ERR_HIP, "hipGetSymbolAddress gave no address for the scratch");
+    g_scratch_addr[dev] = addr;
+  }
+  *out = g_scratch_addr[dev];
   return SPC3D_OK;
 }
 
@@ -164,18 +212,32 @@ spc3d_status spc3d_sddmm_spmm(spc3d_plan h, const float* d_vals, const void* d_A
                               spc3d_dtype ab_t, int32_t kz, float* d_out, float* d_Y, int mode,
                               int variant, void* d_buf, size_t buf_bytes, hipStream_t stream) {
   Plan* p;
-  spc3d_status st = get_plan(h, &p);
+  spc3d_status st = check_fused_args(h, &p, ab_t, kz, mode);
   if (st != SPC3D_OK) return st;
-  if (ab_t != SPC3D_F32 && ab_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad ab_t");
-  if (mode != SPC3D_OVERWRITE && mode != SPC3D_ACCUMULATE)
-    return fail(SPC3D_ERR_INVALID_ARG, "bad mode");
-  if (kz < 1 || kz > kMaxKz) return fail(SPC3D_ERR_INVALID_ARG, "kz=%d outside [1,%d]", kz, kMaxKz);
   if (p->nnz == 0) return SPC3D_OK;
   if (!d_A || !d_B || !d_out || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
   return run_spmm(p, 0, d_vals, d_B, ab_t, kz, d_Y, mode, variant, d_buf, buf_bytes, stream, d_A,
                   d_out);
+}
+
+spc3d_status spc3d_sddmm_spmm_static(spc3d_plan h, const float* d_vals, const void* d_A,
+                                     const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
+                                     float* d_Y, int mode, int variant, hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = check_fused_args(h, &p, ab_t, kz, mode);
+  if (st != SPC3D_OK) return st;
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_A || !d_B || !d_out || !d_Y) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  DeviceGuard dg;
+  st = dg.enter(p);
+  if (st != SPC3D_OK) return st;
+  void* buf = nullptr;
+  st = static_scratch(&buf);
+  if (st != SPC3D_OK) return st;
+  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, d_Y, mode, variant, buf,
+                  SPC3D_STATIC_SCRATCH_BYTES, stream, d_A, d_out, true);
 }
 
 spc3d_status spc3d_variant_check(int op, int32_t kz, spc3d_dtype ab_t, int variant) {

@@ -25,6 +25,7 @@ CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
 OP_SDDMM, OP_SPMM, OP_SDDMM_SPMM = 0, 1, 2
 NFEAT = 23
 FEATURES_BUFFER_BYTES = 256
+STATIC_SCRATCH_BYTES = 8 << 20
 
 
 VARIANT_WINDOW = 0x200
@@ -73,6 +74,8 @@ def lib():
                        vp, sz, vp],
         "spc3d_sddmm_spmm": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int,
                              ctypes.c_int, vp, sz, vp],
+        "spc3d_sddmm_spmm_static": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int,
+                                    ctypes.c_int, vp],
         "spc3d_scatter_reduce": [vp, ctypes.c_int, vp, i32, vp, i64, i32, vp],
         "spc3d_permute_values": [vp, ctypes.c_int, vp, vp, vp],
         "spc3d_row_softmax_buffer_size": [vp, P(sz)],
@@ -358,6 +361,32 @@ def sddmm_spmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | Non
     _check(lib().spc3d_sddmm_spmm(plan.handle, _ptr(vals), _ptr(A), _ptr(B), _dtype_code(A), kz,
                                   _ptr(out), _ptr(Y), mode, variant, _ptr(buf), buf.numel(),
                                   _stream(stream)), "spc3d_sddmm_spmm")
+    return out, Y
+
+
+def sddmm_spmm_static(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | None = None,
+                      out: torch.Tensor | None = None, Y: torch.Tensor | None = None,
+                      mode: int = OVERWRITE, variant: int = -1, stream=None):
+    """sddmm_spmm with the library's static scratch instead of a buffer argument
+    (spc3d_sddmm_spmm_static); returns (out, Y).  The caller provides out and Y
+    when nothing may be allocated."""
+    kz = A.shape[1] if kz is None else kz
+    _need(A.dtype == B.dtype, "A and B must share a dtype")
+    _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
+    _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
+          "vals must hold nnz FP32 values")
+    if out is None:
+        out = torch.empty(plan.nnz, dtype=torch.float32, device=A.device)
+    if Y is None:
+        Y = torch.empty((plan.R, kz), dtype=torch.float32, device=A.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
+          "out must hold nnz FP32 values")
+    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz,
+          "Y too small")
+    _check(lib().spc3d_sddmm_spmm_static(plan.handle, _ptr(vals), _ptr(A), _ptr(B),
+                                         _dtype_code(A), kz, _ptr(out), _ptr(Y), mode, variant,
+                                         _stream(stream)), "spc3d_sddmm_spmm_static")
     return out, Y
 
 
