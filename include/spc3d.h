@@ -56,7 +56,16 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* The enum types below are int-sized.  C++ code sees them with int as fixed
+ * underlying type, so any int a caller passes (say 7 for a dtype) is a value
+ * the library's argument checks can reject, not an out-of-range enum. */
+#ifdef __cplusplus
+#define SPC3D_ENUM enum : int
+#else
+#define SPC3D_ENUM enum
+#endif
+
+typedef SPC3D_ENUM {
   SPC3D_OK = 0,
   SPC3D_ERR_INVALID_ARG = 1,  /* null pointer, bad size, misalignment, bad enum */
   SPC3D_ERR_OUT_OF_RANGE = 2, /* a global id outside [lo, hi) at plan creation */
@@ -66,8 +75,8 @@ typedef enum {
   SPC3D_ERR_BAD_HANDLE = 6    /* not a live plan */
 } spc3d_status;
 
-typedef enum { SPC3D_F32 = 0, SPC3D_BF16 = 1 } spc3d_dtype;
-typedef enum { SPC3D_ROWS = 0, SPC3D_COLS = 1 } spc3d_axis;
+typedef SPC3D_ENUM { SPC3D_F32 = 0, SPC3D_BF16 = 1 } spc3d_dtype;
+typedef SPC3D_ENUM { SPC3D_ROWS = 0, SPC3D_COLS = 1 } spc3d_axis;
 
 enum { SPC3D_OVERWRITE = 0, SPC3D_ACCUMULATE = 1 };  /* output modes */
 enum { SPC3D_BUILD_CSC = 1u };                        /* plan flags */
@@ -234,6 +243,24 @@ spc3d_status spc3d_sddmm_spmm(spc3d_plan plan, const float* d_vals, const void* 
                               const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
                               float* d_Y, int mode, int variant, void* d_buf, size_t buf_bytes,
                               hipStream_t stream);
+
+/* The fused pass with the SpMM PostComm folded in: SDDMM values as
+ * spc3d_sddmm_spmm computes them, and each local row's SpMM sum added straight
+ * into the owner's slab instead of a packed Y (Section "Building SpMM with
+ * SpComm3D": partial rows reduced at their owner; Method 1 unpacking):
+ *   d_out[p] (=|+=) s_p * <A[i(p)], B[j(p)]>            (out_mode)
+ *   d_dst[(gmap_r[i] - row_lo)*ld_dst + k0 + k] += sum_{p in row i} s_p * B[j(p)*kz + k]
+ * for every local row i and k < kz.  Each row sum is complete (summed in the
+ * same order as spc3d_sddmm_spmm) before its single addition, so d_dst ends
+ * bit for bit as after spc3d_sddmm_spmm (OVERWRITE) followed by
+ * spc3d_scatter_reduce(ROWS); rows the block does not touch are unchanged.
+ * Requires 0 <= k0, k0 + kz <= ld_dst; d_dst may not alias an input.  d_buf
+ * holds spc3d_spmm_buffer_size(plan, 0, kz, variant) bytes. */
+spc3d_status spc3d_sddmm_spmm_scatter(spc3d_plan plan, const float* d_vals, const void* d_A,
+                                      const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
+                                      int out_mode, float* d_dst, int64_t ld_dst, int32_t k0,
+                                      int variant, void* d_buf, size_t buf_bytes,
+                                      hipStream_t stream);
 
 /* Bytes of the library's static scratch array (one per GPU) that
  * spc3d_sddmm_spmm_static uses in place of a caller buffer. */

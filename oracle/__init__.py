@@ -17,7 +17,8 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SO names another build of oracle.c (the tests' sanitizer build)
+_SO = os.environ.get("ORACLE_SO") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -39,7 +39,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "libsynth.so")
+# SYNTH_SO names another build of synth.c (the tests' sanitizer build)
+_SO = os.environ.get("SYNTH_SO") or os.path.join(_HERE, "libsynth.so")
 _lib = None
 
 RMAT_ABC = (0.57, 0.19, 0.19)

@@ -8,7 +8,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "spc3d.h")
-LIB = os.path.join(ROOT, "paper_2404_19638_amd", "libspc3d.so")
+# SPC3D_LIB names another build of the library (the host sanitizer build)
+LIB = os.environ.get("SPC3D_LIB") or os.path.join(ROOT, "paper_2404_19638_amd", "libspc3d.so")
 
 
 def declared():
