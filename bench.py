@@ -4,7 +4,11 @@ One step = one iteration of the paper's per-iteration loop on one processor's
 share (PreComm local side, Compute, PostComm local side):
     gather A rows -> gather B rows -> SDDMM -> SpMM -> scatter-reduce
 over a localized block built once beforehand (the setup phase, timed and
-reported separately).  Default workload: one processor's 3D share of an R-MAT
+reported separately).  By default SDDMM and SpMM run as one pass followed by
+the scatter-reduce; --fused 2 folds the scatter-reduce into the pass (each
+SpMM row added into the owner's slab as it completes, bit-identical) and
+--fused 0 runs every step separately.  All three forms are timed and
+reported under step_forms.  Default workload: one processor's 3D share of an R-MAT
 graph (2^24 vertices, average degree 16) on an 8x8x4 grid, i.e. a 2^21 x 2^21
 block with ~4M entries, K = 128 and the local K-slice kz = 32, FP32.
 
@@ -57,6 +61,9 @@ def algorithmic_bytes(R, C, nnz, kz, b):
         "scatter": 8 * R + 12 * kz * R,
         # one pass: S structure, values and B rows read once for both products
         "sddmm_spmm": 4 * (R + 1) + 12 * nnz + kz * b * (R + C) + 4 * kz * R,
+        # the same pass adding each row into the owner's slab: the slab rows
+        # read and written, and the row map, in place of the packed Y
+        "sddmm_spmm_scatter": 4 * (R + 1) + 12 * nnz + kz * b * (R + C) + 8 * R + 8 * kz * R,
     }
 
 
@@ -144,9 +151,10 @@ def copy_bandwidth(dev, mib=1024, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def cold_kernels(step, names, spans, nev, alg, steps, dev):
-    """Per-kernel event times with L2 and the Infinity Cache flushed before
-    each step by a 1 GiB write (the flush itself is outside the events)."""
+def cold_steps(step, names, spans, nev, alg, steps, dev, flops):
+    """The step and each kernel with L2 and the Infinity Cache flushed before
+    every step by a 1 GiB write (the flush is outside the events, which
+    bracket the step from its first kernel to its last)."""
     import numpy as np
     import torch
 
@@ -158,14 +166,22 @@ def cold_kernels(step, names, spans, nev, alg, steps, dev):
         step(ev)
         evs.append(ev)
     torch.cuda.synchronize()
-    out = {}
+    kernels = {}
     for n in names:
         a, b = spans[n]
         ms = float(np.mean([e[a].elapsed_time(e[b]) for e in evs]))
-        out[n] = {"ms": round(ms, 5), "GB_s": round(alg[n] / (ms * 1e-3) / 1e9, 1),
-                  "frac_hbm": round(alg[n] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        kernels[n] = {"ms": round(ms, 5), "GB_s": round(alg[n] / (ms * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(alg[n] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    step_ms = float(np.mean([e[0].elapsed_time(e[nev - 1]) for e in evs]))
+    total = sum(alg[n] for n in names)
+    dom = max(names, key=lambda n: kernels[n]["ms"])
     del flush
-    return out
+    return {"steps": steps, "step_ms": round(step_ms, 5),
+            "value": round(flops / (step_ms * 1e-3) / 1e9, 2),
+            "step_frac_hbm": round(total / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"],
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": kernels[dom]["frac_hbm"]},
+            "kernels": kernels}
 
 
 def forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_main, per_main, flops):
@@ -201,9 +217,9 @@ def forms(args, spc, plan, kz, nnz, make_step, timed, names, ms_main, per_main, 
             out[f"{dt}_{tag}"] = {"variant": list(v) if isinstance(v, tuple) else v,
                                   "chosen_by": how, "ms_per_step": round(ms, 5),
                                   "value": round(flops / (ms * 1e-3) / 1e9, 2),
-                                  "compute_kernel_ms": round(per[names[2]], 5)
-                                  if len(names) == 4 else
-                                  round(per[names[2]] + per[names[3]], 5),
+                                  "compute_kernel_ms": round(sum(per[n] for n in names
+                                                                 if not n.startswith("gather")
+                                                                 and n != "scatter"), 5),
                                   "dominant": dom, "error_bar": ERROR_BARS[dt]}
     return out
 
@@ -227,8 +243,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="time the K steps as replays of one step captured in a HIP graph "
                          "(both are always measured and reported under 'launch')")
-    ap.add_argument("--fused", type=int, default=1,
-                    help="1: one fused SDDMM+SpMM pass per step; 0: separate kernels")
+    ap.add_argument("--fused", type=int, default=1, choices=[0, 1, 2],
+                    help="2: one pass for SDDMM, SpMM and the scatter-reduce; 1: a fused "
+                         "SDDMM+SpMM pass and the scatter-reduce; 0: separate kernels")
     ap.add_argument("--workload", choices=["share3d", "uniform", "banded", "tiny", "precision"],
                     default="share3d",
                     help="share3d: one processor's block of R-MAT 2^24 (the benchmark); "
@@ -307,20 +324,28 @@ def main():
     log(f"bench: plan R={R} C={C} nnz={nnz} setup {setup_ms:.1f} ms (first), "
         f"{setup_warm_ms:.2f} ms (again)")
 
-    if args.fused:
-        names = ["gather_A", "gather_B", "sddmm_spmm", "scatter"]
-    else:
-        names = ["gather_A", "gather_B", "sddmm", "spmm", "scatter"]
-
     # Events: 0 start, 1 after gather A, 2 / 3 around gather B, 4 start of the
     # compute, then one after each remaining kernel.  (Running the two packs on
     # two streams was measured slower than one after the other: they contend
     # for the same HBM bandwidth.)
-    nev = len(names) + 3
+    def layout(kind):
+        """Kernels of a step form, kernel -> (start event, end event), event count."""
+        spans = {"gather_A": (0, 1), "gather_B": (2, 3)}
+        if kind == 2:
+            spans.update(sddmm_spmm_scatter=(4, 5))
+        elif kind == 1:
+            spans.update(sddmm_spmm=(4, 5), scatter=(5, 6))
+        else:
+            spans.update(sddmm=(4, 5), spmm=(5, 6), scatter=(6, 7))
+        return list(spans), spans, len(spans) + 3
 
-    def make_step(dtype, variant):
-        """One step in dtype; variant is an int, or (SDDMM, SpMM) variants when unfused.
-        step(ev) records events ev[0..nev) and returns {kernel: (start, end)} indices."""
+    names, spans, nev = layout(args.fused)
+
+    def make_step(dtype, variant, kind=None):
+        """One step in dtype; variant is an int, or (SDDMM, SpMM) variants when unfused;
+        kind the step form (default --fused).  step(ev) records events ev[0..nev)."""
+        kind = args.fused if kind is None else kind
+        last = layout(kind)[2] - 1
         v_sd, v_sp = variant if isinstance(variant, tuple) else (variant, variant)
         pdt = torch.float32 if dtype == "f32" else torch.bfloat16
         A_loc = torch.empty((R, kz), dtype=pdt, device=dev)
@@ -341,32 +366,31 @@ def main():
             spc.gather(plan, spc.COLS, B_src, k0, kz, out=B_loc)
             mark(3)
             mark(4)
-            if args.fused:
+            if kind == 2:
+                spc.sddmm_spmm_scatter(plan, vals, A_loc, B_loc, Y_dst, k0, kz, out=out,
+                                       variant=v_sp, buf=spbuf)
+            elif kind == 1:
                 spc.sddmm_spmm(plan, vals, A_loc, B_loc, kz, out=out, Y=Y_loc, variant=v_sp,
                                buf=spbuf)
                 mark(5)
+                spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
             else:
                 spc.sddmm(plan, vals, A_loc, B_loc, kz, out=out, variant=v_sd)
                 mark(5)
                 spc.spmm(plan, vals, B_loc, 0, kz, out=Y_loc, variant=v_sp, buf=spbuf)
                 mark(6)
-            spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
-            mark(nev - 1)
+                spc.scatter_reduce(plan, spc.ROWS, Y_loc, Y_dst, k0)
+            mark(last)
         return step
-
-    # kernel -> (start event, end event); every pair is on the stream the kernel runs on
-    spans = {"gather_A": (0, 1), "gather_B": (2, 3)}
-    if args.fused:
-        spans.update(sddmm_spmm=(4, 5), scatter=(5, 6))
-    else:
-        spans.update(sddmm=(4, 5), spmm=(5, 6), scatter=(6, 7))
 
     spread = {}   # kernel -> (median, min) ms of the last timed() call
 
-    def timed(step, steps, warmup):
+    def timed(step, steps, warmup, kind=None):
         """Step time from exactly `steps` steps with nothing recorded between them
         (the timing markers of the per-kernel pass add gaps between kernels), then
-        per-kernel times from a second pass with events around every kernel."""
+        per-kernel times from a second pass with events around every kernel
+        (every event pair is on the stream the kernels run on)."""
+        _, spans_k, nev_k = layout(args.fused if kind is None else kind)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -375,13 +399,13 @@ def main():
             step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)]
+        events = [[torch.cuda.Event(enable_timing=True) for _ in range(nev_k)]
                   for _ in range(steps)]
         for i in range(steps):
             step(events[i])
         torch.cuda.synchronize()
         samples = {n: [events[i][a].elapsed_time(events[i][b]) for i in range(steps)]
-                   for n, (a, b) in spans.items()}
+                   for n, (a, b) in spans_k.items()}
         per = {n: float(np.mean(v)) for n, v in samples.items()}
         spread.clear()
         spread.update({n: (float(np.median(v)), float(np.min(v))) for n, v in samples.items()})
@@ -453,8 +477,10 @@ def main():
                       {"rmat_scale": 22, "avg_degree": 32, "grid": "1x1x1"}
                       if args.workload == "precision" else {"grid": "1x1x1"}),
                    "R": R, "C": C, "nnz": nnz, "K": p.K, "kz": kz, "k0": k0,
-                   "step": ("gather A, gather B, fused SDDMM+SpMM, scatter-reduce" if args.fused
-                            else "gather A, gather B, SDDMM, SpMM, scatter-reduce"),
+                   "step": {2: "gather A, gather B, one pass of SDDMM+SpMM with the "
+                                "scatter-reduce folded in",
+                            1: "gather A, gather B, fused SDDMM+SpMM, scatter-reduce",
+                            0: "gather A, gather B, SDDMM, SpMM, scatter-reduce"}[args.fused],
                    "local_row_order": (f"owner-grouped, {args.row_groups} groups"
                                        if args.row_groups else "ascending global id")},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
@@ -472,9 +498,20 @@ def main():
         "setup_warm_ms": round(setup_warm_ms, 3),
         "source_hash": src_hash,
     }
+    # the other forms of the same step (the same results; the scatter-reduce
+    # folded into the pass, or each kernel on its own)
+    res["step_forms"] = {}
+    for kind in (2, 1, 0):
+        if kind == args.fused:
+            ms_k = ms_per_step
+        else:
+            ms_k, _ = timed(make_step(args.dtype, args.variant, kind), args.steps, args.warmup,
+                            kind)
+        res["step_forms"][{2: "scatter_folded", 1: "fused_then_scatter", 0: "separate"}[kind]] = {
+            "ms_per_step": round(ms_k, 5), "value": round(flops / (ms_k * 1e-3) / 1e9, 2)}
     if args.cold_steps:
-        res["cold"] = cold_kernels(make_step(args.dtype, args.variant), names, spans, nev, alg,
-                                   args.cold_steps, dev)
+        res["cold"] = cold_steps(make_step(args.dtype, args.variant), names, spans, nev, alg,
+                                 args.cold_steps, dev, flops)
     if not args.no_forms:
         res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, eager_ms,
                              per_kernel_ms, flops)

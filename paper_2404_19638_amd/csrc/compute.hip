@@ -19,15 +19,17 @@ SPC3D_EXTERN_LAUNCHERS(bf16_t, 1)
 
 namespace {
 
-// Shared body of spc3d_spmm, spc3d_sddmm_spmm and spc3d_sddmm_spmm_static
-// (static_buf: d_buf is the library's own scratch array).
+// Shared body of spc3d_spmm, spc3d_sddmm_spmm, spc3d_sddmm_spmm_static and
+// spc3d_sddmm_spmm_scatter.  Y: where finished rows go; acc: kAccY / kAccOut
+// bits; static_buf: d_buf is the library's own scratch array.
 spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d_X,
-                      spc3d_dtype x_t, int32_t kz, float* d_Y, int mode, int variant, void* d_buf,
-                      size_t buf_bytes, hipStream_t stream, const void* d_A, float* d_out,
-                      bool static_buf = false) {
+                      spc3d_dtype x_t, int32_t kz, const YOut& Y, int acc, int variant,
+                      void* d_buf, size_t buf_bytes, hipStream_t stream, const void* d_A,
+                      float* d_out, bool static_buf = false) {
   const bool fused = d_A != nullptr;
   Shape sh;
-  const bool al = aligned16(d_X) && aligned16(d_Y) && (!fused || aligned16(d_A));
+  const bool al = aligned16(d_X) && aligned16(Y.base) && Y.ld % 4 == 0 &&
+                  (!fused || aligned16(d_A));
   spc3d_status st = pick_shape(kz, x_t, al, variant, fused ? 2 : 1, p->nnz, &sh);
   if (st != SPC3D_OK) return st;
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
@@ -46,16 +48,15 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   if (st != SPC3D_OK) return st;
   const int64_t nblocks = (nitems + 3) / 4;
   const Orient o = transpose ? p->csc() : p->csr();
-  const int acc = mode == SPC3D_ACCUMULATE;
   float* carry = static_cast<float*>(d_buf);
 #define SPC3D_RUN(T, V)                                                                        \
   do {                                                                                         \
     if (fused)                                                                                 \
-      launch_spmm<T, V, true>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y,    \
-                              acc, carry, lds, d_A, d_out);                                    \
+      launch_spmm<T, V, true>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, Y, acc, \
+                              carry, lds, d_A, d_out);                                         \
     else                                                                                       \
-      launch_spmm<T, V, false>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, d_Y,   \
-                               acc, carry, lds, nullptr, nullptr);                             \
+      launch_spmm<T, V, false>(sh, stream, p->nnz, nitems, nblocks, o, d_vals, d_X, kz, Y, acc,\
+                               carry, lds, nullptr, nullptr);                                  \
   } while (0)
   if (x_t == SPC3D_F32) {
     if (sh.vec == 4) SPC3D_RUN(float, 4);
@@ -69,7 +70,10 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   return SPC3D_OK;
 }
 
-// Arguments common to spc3d_sddmm_spmm and spc3d_sddmm_spmm_static.
+// The kernels' accumulate bits for an output mode that applies to both outputs.
+int acc_bits(int mode) { return mode == SPC3D_ACCUMULATE ? (kAccY | kAccOut) : 0; }
+
+// Arguments common to the fused entry points.
 spc3d_status check_fused_args(spc3d_plan h, Plan** p, spc3d_dtype ab_t, int32_t kz, int mode) {
   spc3d_status st = get_plan(h, p);
   if (st != SPC3D_OK) return st;
@@ -204,8 +208,9 @@ spc3d_status spc3d_spmm(spc3d_plan h, int transpose, const float* d_vals, const 
   if (!d_X || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
-  return run_spmm(p, transpose, d_vals, d_X, x_t, kz, d_Y, mode, variant, d_buf, buf_bytes,
-                  stream, nullptr, nullptr);
+  const YOut Y{d_Y, nullptr, 0, kz, 0};
+  return run_spmm(p, transpose, d_vals, d_X, x_t, kz, Y, acc_bits(mode), variant, d_buf,
+                  buf_bytes, stream, nullptr, nullptr);
 }
 
 spc3d_status spc3d_sddmm_spmm(spc3d_plan h, const float* d_vals, const void* d_A, const void* d_B,
@@ -218,8 +223,9 @@ spc3d_status spc3d_sddmm_spmm(spc3d_plan h, const float* d_vals, const void* d_A
   if (!d_A || !d_B || !d_out || !d_Y || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
     return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
-  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, d_Y, mode, variant, d_buf, buf_bytes, stream, d_A,
-                  d_out);
+  const YOut Y{d_Y, nullptr, 0, kz, 0};
+  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, Y, acc_bits(mode), variant, d_buf, buf_bytes,
+                  stream, d_A, d_out);
 }
 
 spc3d_status spc3d_sddmm_spmm_static(spc3d_plan h, const float* d_vals, const void* d_A,
@@ -236,8 +242,30 @@ spc3d_status spc3d_sddmm_spmm_static(spc3d_plan h, const float* d_vals, const vo
   void* buf = nullptr;
   st = static_scratch(&buf);
   if (st != SPC3D_OK) return st;
-  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, d_Y, mode, variant, buf,
+  const YOut Y{d_Y, nullptr, 0, kz, 0};
+  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, Y, acc_bits(mode), variant, buf,
                   SPC3D_STATIC_SCRATCH_BYTES, stream, d_A, d_out, true);
+}
+
+spc3d_status spc3d_sddmm_spmm_scatter(spc3d_plan h, const float* d_vals, const void* d_A,
+                                      const void* d_B, spc3d_dtype ab_t, int32_t kz, float* d_out,
+                                      int out_mode, float* d_dst, int64_t ld_dst, int32_t k0,
+                                      int variant, void* d_buf, size_t buf_bytes,
+                                      hipStream_t stream) {
+  Plan* p;
+  spc3d_status st = check_fused_args(h, &p, ab_t, kz, out_mode);
+  if (st != SPC3D_OK) return st;
+  if (k0 < 0 || ld_dst < (int64_t)k0 + kz)
+    return fail(SPC3D_ERR_INVALID_ARG, "k0=%d kz=%d do not fit ld_dst=%lld", k0, kz,
+                (long long)ld_dst);
+  if (p->nnz == 0) return SPC3D_OK;
+  if (!d_A || !d_B || !d_out || !d_dst || !d_buf) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(d_buf) & 255u)
+    return fail(SPC3D_ERR_INVALID_ARG, "buffer must be 256-byte aligned");
+  const YOut Y{d_dst + k0, p->gmap_r, p->row_lo, ld_dst, p->R};
+  const int acc = kAccY | (out_mode == SPC3D_ACCUMULATE ? kAccOut : 0);
+  return run_spmm(p, 0, d_vals, d_B, ab_t, kz, Y, acc, variant, d_buf, buf_bytes, stream, d_A,
+                  d_out);
 }
 
 spc3d_status spc3d_variant_check(int op, int32_t kz, spc3d_dtype ab_t, int variant) {

@@ -172,14 +172,16 @@ __global__ __launch_bounds__(256) void k_sddmm(int64_t nnz, int64_t nitems, int6
 
 // ------------------------------------------------------------------- SpMM
 
+// Stores (or, with accumulate, adds) this lane's part of a finished row sum
+// at yr, the first element of the destination row.
 template <int VEC, int NCH>
-__device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int nvec, int q,
-                                 int lpn, const float (&acc)[NCH][VEC], int accumulate) {
+__device__ inline void store_row_at(float* __restrict__ yr, int nvec, int q, int lpn,
+                                    const float (&acc)[NCH][VEC], int accumulate) {
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
     const int vi = q + ch * lpn;
     if (vi < nvec) {
-      float* y = Y + row * kz + vi * VEC;
+      float* y = yr + vi * VEC;
       if constexpr (VEC % 4 == 0) {
 #pragma unroll
         for (int t = 0; t < VEC; t += 4) {
@@ -190,6 +192,73 @@ __device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int
       } else {
 #pragma unroll
         for (int t = 0; t < VEC; ++t) y[t] = accumulate ? y[t] + acc[ch][t] : acc[ch][t];
+      }
+    }
+  }
+}
+
+template <int VEC, int NCH>
+__device__ inline void store_row(float* __restrict__ Y, int64_t row, int kz, int nvec, int q,
+                                 int lpn, const float (&acc)[NCH][VEC], int accumulate) {
+  store_row_at<VEC, NCH>(Y + row * kz, nvec, q, lpn, acc, accumulate);
+}
+
+// Where the SpMM kernels put a finished row r: at base + r * ld (the packed
+// Y_loc, ld = kz), or, with map set, added into the owner's slab at
+// base + (map[r] - lo) * ld, which is the PostComm scatter-reduce of Y_loc
+// done as each row completes (base then points at column k0 of row lo).
+// Every row is finished, and so stored, exactly once.
+struct YOut {
+  float* base;
+  const int64_t* map;
+  int64_t lo;
+  int64_t ld;
+  int64_t n;   // entries of map (the local rows)
+};
+
+// Bits of the kernels' accumulate argument: add SpMM rows into the
+// destination; add SDDMM values into out (the fused pass).
+enum { kAccY = 1, kAccOut = 2 };
+
+template <int VEC, int NCH>
+__device__ inline void store_row(const YOut& Y, int64_t row, int /*kz*/, int nvec, int q, int lpn,
+                                 const float (&acc)[NCH][VEC], int accumulate) {
+  const int64_t r = Y.map ? Y.map[row] - Y.lo : row;
+  store_row_at<VEC, NCH>(Y.base + r * Y.ld, nvec, q, lpn, acc, accumulate & kAccY);
+}
+
+// This lane's part of a destination row (VEC a multiple of 4), loaded ahead of
+// the addition that completes the row.
+template <int VEC, int NCH>
+__device__ inline void load_dst(const float* __restrict__ yr, int nvec, int q, int lpn,
+                                float (&pre)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; t += 4) {
+        const f32x4 v = ld_stream(reinterpret_cast<const f32x4*>(yr + vi * VEC + t));
+        pre[ch][t] = v.x; pre[ch][t + 1] = v.y; pre[ch][t + 2] = v.z; pre[ch][t + 3] = v.w;
+      }
+    }
+  }
+}
+
+// yr = pre + acc, the finished row added to the destination values loaded
+// when the row started (the same FP32 addition as a read-modify-write).
+template <int VEC, int NCH>
+__device__ inline void store_pre(float* __restrict__ yr, int nvec, int q, int lpn,
+                                 const float (&pre)[NCH][VEC], const float (&acc)[NCH][VEC]) {
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    const int vi = q + ch * lpn;
+    if (vi < nvec) {
+#pragma unroll
+      for (int t = 0; t < VEC; t += 4) {
+        const f32x4 o = {pre[ch][t] + acc[ch][t], pre[ch][t + 1] + acc[ch][t + 1],
+                         pre[ch][t + 2] + acc[ch][t + 2], pre[ch][t + 3] + acc[ch][t + 3]};
+        st_stream(reinterpret_cast<f32x4*>(yr + vi * VEC + t), o);
       }
     }
   }
@@ -290,7 +359,10 @@ __device__ inline void load_batch(Batch<T, VEC, LPN, NCH, UB, FUSED>& bt, int64_
 
 // SpMM (and, with FUSED, SDDMM on the same pass: every slot's packed B row is
 // read once and used both for the dot with its A row and for the row sum).
-template <typename T, int VEC, int LPN, int NCH, bool FUSED, int UBT>
+// SC (rows added into the owner's slab through Y.map): each row's destination
+// values are loaded when the row starts, one row's map entry ahead, so the
+// addition at the row's end issues a store instead of waiting for a load.
+template <typename T, int VEC, int LPN, int NCH, bool FUSED, int UBT, bool SC = false>
 __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64_t nblocks,
                                               int wslots, const int32_t* __restrict__ idx,
                                               const uint64_t* __restrict__ head,
@@ -298,7 +370,7 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
                                               const float* __restrict__ vals,
                                               const int32_t* __restrict__ vidx,
                                               const T* __restrict__ X, int kz,
-                                              float* __restrict__ Y, int accumulate,
+                                              YOut Y, int accumulate,
                                               float* __restrict__ carry, const T* __restrict__ A,
                                               float* __restrict__ out) {
   constexpr int G = 64 / LPN;
@@ -352,9 +424,19 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
   int cur = 0;
   const int64_t gs = b + (int64_t)g * S;
   const int64_t ge = (gs + S < e) ? gs + S : e;
+  float pre[SC ? NCH : 1][VEC];   // SC: destination values of row cur
+  float* ycur = nullptr;          // SC: destination row of cur
+  int64_t gnext = 0;              // SC: map entry of row cur + 1
   if (active && gs < ge) {
     cur = row_of(head, tile_row, gs);
     started = is_head(head, gs);
+    if constexpr (SC) {
+      gnext = cur + 1 < Y.n ? Y.map[cur + 1] : 0;
+      if (started) {
+        ycur = Y.base + (Y.map[cur] - Y.lo) * Y.ld;
+        load_dst<VEC, NCH>(ycur, nvec, q, LPN, pre);
+      }
+    }
     BT cb;
     float acur[FUSED ? NCH : 1][VEC];
     for (int64_t s0 = gs; s0 < ge; s0 += UB) {
@@ -379,7 +461,10 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
         if (s0 + u < ge) {
           if (s0 + u > gs && ((cb.hbits >> u) & 1u)) {
             if (started) {
-              store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
+              if constexpr (SC)
+                store_pre<VEC, NCH>(ycur, nvec, q, LPN, pre, acc);
+              else
+                store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
             } else {
               store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
               kind = kLeadEnds;
@@ -387,6 +472,11 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
             zero(acc);
             ++cur;
             started = true;
+            if constexpr (SC) {
+              ycur = Y.base + (gnext - Y.lo) * Y.ld;
+              load_dst<VEC, NCH>(ycur, nvec, q, LPN, pre);
+              gnext = cur + 1 < Y.n ? Y.map[cur + 1] : 0;
+            }
           }
 #pragma unroll
           for (int ch = 0; ch < NCH; ++ch)
@@ -397,10 +487,12 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
     }
     const bool ends = (ge >= nnz) || is_head(head, ge);
     if (started) {
-      if (ends)
-        store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
-      else
+      if (!ends)
         tail = true;
+      else if constexpr (SC)
+        store_pre<VEC, NCH>(ycur, nvec, q, LPN, pre, acc);
+      else
+        store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
     } else {
       store_vec<VEC, NCH>(s_lead + g * KW, nvec, q, LPN, acc);
       kind = ends ? kLeadEnds : kLeadThrough;
@@ -412,8 +504,8 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
 
   if constexpr (FUSED) {
     for (int i = lane; i < (int)(e - b); i += 64)
-      st_stream(out + b + i, accumulate ? ld_stream(out + b + i) + s_out[i + (i >> lgS)]
-                                        : s_out[i + (i >> lgS)]);
+      st_stream(out + b + i, (accumulate & kAccOut) ? ld_stream(out + b + i) + s_out[i + (i >> lgS)]
+                                                    : s_out[i + (i >> lgS)]);
   }
   if (tail) {
     bool done = false;
@@ -426,10 +518,12 @@ __global__ __launch_bounds__(256) void k_spmm(int64_t nnz, int64_t nitems, int64
         break;
       }
     }
-    if (done)
-      store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
-    else
+    if (!done)
       store_vec<VEC, NCH>(carry + (item * 2 + 1) * kz, nvec, q, LPN, acc);
+    else if constexpr (SC)
+      store_pre<VEC, NCH>(ycur, nvec, q, LPN, pre, acc);
+    else
+      store_row<VEC, NCH>(Y, cur, kz, nvec, q, LPN, acc, accumulate);
   }
   if (g == 0 && s_kind[0] != kLeadNone) {
     float hc[NCH][VEC];
@@ -480,7 +574,7 @@ __global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int6
                                                const float* __restrict__ vals,
                                                const int32_t* __restrict__ vidx,
                                                const T* __restrict__ X, int kz,
-                                               float* __restrict__ Y, int accumulate,
+                                               YOut Y, int accumulate,
                                                float* __restrict__ carry,
                                                const T* __restrict__ A,
                                                float* __restrict__ out) {
@@ -578,7 +672,7 @@ __global__ __launch_bounds__(256) void k_wspmm(int64_t nnz, int64_t nitems, int6
     if constexpr (FUSED) {
       if (valid) {
         const float o = v * res;
-        st_stream(out + sl, accumulate ? ld_stream(out + sl) + o : o);
+        st_stream(out + sl, (accumulate & kAccOut) ? ld_stream(out + sl) + o : o);
       }
     }
 
@@ -681,7 +775,7 @@ __global__ __launch_bounds__(256) void k_spmm_fixup(int64_t nnz, int64_t nitems,
                                                     const int32_t* __restrict__ ptr,
                                                     const uint64_t* __restrict__ head,
                                                     const int32_t* __restrict__ tile_row, int kz,
-                                                    float* __restrict__ Y, int accumulate,
+                                                    YOut Y, int accumulate,
                                                     const float* __restrict__ carry) {
   constexpr int G = 64 / LPN;
   constexpr int BLK = 16;
@@ -860,7 +954,7 @@ void launch_sddmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, 
 
 template <typename T, int VEC, bool FUSED>
 void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, int64_t nblocks,
-                 const Orient& o, const float* vals, const void* X, int kz, float* Y,
+                 const Orient& o, const float* vals, const void* X, int kz, const YOut& Y,
                  int accumulate, float* carry, size_t lds, const void* A, float* out) {
   SPC3D_SWITCH_LPN(sh.lanes, SPC3D_SWITCH_NCH(sh.nch,
       if (sh.window) {
@@ -875,7 +969,15 @@ void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, i
                            dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
                            o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
                            carry, static_cast<const T*>(A), out);
-      else
+      else if (FUSED && VEC % 4 == 0 && Y.map) {
+        // rows added into the owner's slab: destination rows loaded ahead
+        if constexpr (FUSED && VEC % 4 == 0)
+          hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, 8, true>),
+                             dim3((unsigned)nblocks), dim3(256), lds, st, nnz, nitems, nblocks,
+                             sh.items, o.idx, o.head, o.tile_row, vals, o.vidx,
+                             static_cast<const T*>(X), kz, Y, accumulate, carry,
+                             static_cast<const T*>(A), out);
+      } else
         hipLaunchKernelGGL((k_spmm<T, VEC, LPN_, NCH_, FUSED, 8>), dim3((unsigned)nblocks),
                            dim3(256), lds, st, nnz, nitems, nblocks, sh.items, o.idx, o.head,
                            o.tile_row, vals, o.vidx, static_cast<const T*>(X), kz, Y, accumulate,
@@ -890,6 +992,6 @@ void launch_spmm(const Shape& sh, hipStream_t st, int64_t nnz, int64_t nitems, i
       const void*, int, float*, int
 #define SPC3D_SPMM_LAUNCH_ARGS                                                                 \
   const Shape&, hipStream_t, int64_t, int64_t, int64_t, const Orient&, const float*, const void*, \
-      int, float*, int, float*, size_t, const void*, float*
+      int, const YOut&, int, float*, size_t, const void*, float*
 
 }  // namespace spc3d

@@ -74,6 +74,8 @@ def lib():
                        vp, sz, vp],
         "spc3d_sddmm_spmm": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int,
                              ctypes.c_int, vp, sz, vp],
+        "spc3d_sddmm_spmm_scatter": [vp, vp, vp, vp, ctypes.c_int, i32, vp, ctypes.c_int, vp,
+                                     i64, i32, ctypes.c_int, vp, sz, vp],
         "spc3d_sddmm_spmm_static": [vp, vp, vp, vp, ctypes.c_int, i32, vp, vp, ctypes.c_int,
                                     ctypes.c_int, vp],
         "spc3d_scatter_reduce": [vp, ctypes.c_int, vp, i32, vp, i64, i32, vp],
@@ -362,6 +364,37 @@ def sddmm_spmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | Non
                                   _ptr(out), _ptr(Y), mode, variant, _ptr(buf), buf.numel(),
                                   _stream(stream)), "spc3d_sddmm_spmm")
     return out, Y
+
+
+def sddmm_spmm_scatter(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, dst: torch.Tensor,
+                       k0: int, kz: int | None = None, out: torch.Tensor | None = None,
+                       out_mode: int = OVERWRITE, variant: int = -1,
+                       buf: torch.Tensor | None = None, stream=None):
+    """SDDMM into out (slot order) and the SpMM rows added into the owner's
+    slab dst (rows gmap_r - row_lo, columns k0..k0+kz) in one pass: the fused
+    pass and spc3d_scatter_reduce(ROWS) together.  Returns out."""
+    kz = A.shape[1] if kz is None else kz
+    _need(A.dtype == B.dtype, "A and B must share a dtype")
+    _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
+    _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
+          "vals must hold nnz FP32 values")
+    _need(dst.dim() == 2 and dst.stride(1) == 1 and dst.dtype == torch.float32,
+          "dst must be a row-major FP32 2-D tensor")
+    _need(dst.shape[0] >= plan.row_range[1] - plan.row_range[0],
+          "dst needs one row per id of the row range")
+    if out is None:
+        out = torch.empty(plan.nnz, dtype=torch.float32, device=A.device)
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
+          "out must hold nnz FP32 values")
+    need = spmm_buffer_size(plan, 0, kz, variant)
+    if buf is None:
+        buf = plan.buffer(("spmm", 0), need)
+    _check(lib().spc3d_sddmm_spmm_scatter(plan.handle, _ptr(vals), _ptr(A), _ptr(B),
+                                          _dtype_code(A), kz, _ptr(out), out_mode, _ptr(dst),
+                                          dst.stride(0), k0, variant, _ptr(buf), buf.numel(),
+                                          _stream(stream)), "spc3d_sddmm_spmm_scatter")
+    return out
 
 
 def sddmm_spmm_static(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | None = None,

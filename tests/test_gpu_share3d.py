@@ -85,6 +85,17 @@ def test_share3d_step_full_size(share):
     oracle.scatter_add_f32(ref["gmap_r"], p.row_range[0], _np(Y), want, k0)
     spc.scatter_reduce(plan, spc.ROWS, Y, dst, k0)
     np.testing.assert_array_equal(_np(dst).view(np.uint32), want.view(np.uint32))
+    # the same PostComm folded into the fused pass (the step bench.py times):
+    # the slab ends bit for bit as the oracle's FP32 addition of the fused
+    # pass's own rows, and the SDDMM values are the fused pass's
+    _say("share3d fused pass with the scatter-reduce folded in")
+    out_f, Y_f = spc.sddmm_spmm(plan, vals, A, B, kz)
+    want = p.A_src.copy()
+    oracle.scatter_add_f32(ref["gmap_r"], p.row_range[0], _np(Y_f), want, k0)
+    dst = torch.from_numpy(p.A_src).to(DEV)
+    out_s = spc.sddmm_spmm_scatter(plan, vals, A, B, dst, k0, kz)
+    np.testing.assert_array_equal(_np(dst).view(np.uint32), want.view(np.uint32))
+    assert torch.equal(out_s.view(torch.int32), out_f.view(torch.int32))
 
 
 def test_share3d_identities_full_size(share):
