@@ -80,7 +80,8 @@ typedef SPC3D_ENUM { SPC3D_ROWS = 0, SPC3D_COLS = 1 } spc3d_axis;
 
 enum { SPC3D_OVERWRITE = 0, SPC3D_ACCUMULATE = 1 };  /* output modes */
 enum { SPC3D_BUILD_CSC = 1u };                        /* plan flags */
-enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1 };
+enum { SPC3D_CALLER_TO_SLOT = 0, SPC3D_SLOT_TO_CALLER = 1,   /* spc3d_permute_values */
+       SPC3D_SLOT_TO_COLUMN = 2, SPC3D_COLUMN_TO_SLOT = 3 };
 
 /* Kernel variant for sddmm / spmm / sddmm_spmm: -1 lets the library choose
  * from kz, the operand type and the block's nnz;
@@ -221,8 +222,11 @@ spc3d_status spc3d_spmm_buffer_size(spc3d_plan plan, int transpose, int32_t kz, 
  *                   X [C x kz], Y [R x kz];
  *   transpose = 1:  Y[j*kz + k] (=|+=) sum_{p in column j} s_p * X[i(p)*kz + k],
  *                   X [R x kz], Y [C x kz]  (needs a plan built with
- *                   SPC3D_BUILD_CSC; used by the backward of SDDMM / SpMM).
- * d_vals[nnz] FP32 in slot order (NULL: s == 1).  X of type x_t (F32 or BF16),
+ *                   SPC3D_BUILD_CSC; used by the backward of SDDMM / SpMM);
+ *   transpose = 2:  as 1, with d_vals in column-major order (as
+ *                   spc3d_permute_values SLOT_TO_COLUMN gives), read as one
+ *                   stream instead of through the slot map; same results.
+ * d_vals[nnz] FP32 in slot order (NULL: s == 1) unless transpose = 2.  X of type x_t (F32 or BF16),
  * accumulation and Y in FP32.  Long rows are split across wavefronts and their
  * partial sums combined in a fixed order, so results are deterministic.
  * d_buf (256-byte aligned) holds at least spc3d_spmm_buffer_size bytes.
@@ -293,8 +297,10 @@ spc3d_status spc3d_scatter_reduce(spc3d_plan plan, spc3d_axis axis, const float*
                                   hipStream_t stream);
 
 /* Move per-entry FP32 values between caller (COO) order and slot order:
- * CALLER_TO_SLOT: out[p] = in[perm[p]];  SLOT_TO_CALLER: out[perm[p]] = in[p].
- * in and out must not alias. */
+ * CALLER_TO_SLOT: out[p] = in[perm[p]];  SLOT_TO_CALLER: out[perm[p]] = in[p];
+ * or between slot order and the column-major order of a plan built with
+ * SPC3D_BUILD_CSC: SLOT_TO_COLUMN: out[t] = in[slot_t[t]];
+ * COLUMN_TO_SLOT: out[slot_t[t]] = in[t].  in and out must not alias. */
 spc3d_status spc3d_permute_values(spc3d_plan plan, int direction, const float* d_in,
                                   float* d_out, hipStream_t stream);
 

@@ -33,6 +33,17 @@ def _needs(ctx, i):
     return ctx.needs_input_grad[i]
 
 
+def _spmm_t(plan, vals, X):
+    """Transposed SpMM (sum over each column's entries).  Values are first
+    permuted to column-major order so the kernel reads them as one stream
+    rather than one random load per entry through the slot map (the same
+    results, bit for bit)."""
+    if vals is None:
+        return spc.spmm(plan, None, X, transpose=1)
+    vt = spc.permute_values(plan, spc.SLOT_TO_COLUMN, vals)
+    return spc.spmm(plan, vt, X, transpose=2)
+
+
 def _as(grad, like):
     """A gradient (FP32 from the library) in the type of its input: with
     bfloat16 operands the products still accumulate in FP32 and only the
@@ -66,7 +77,7 @@ class SDDMMFn(torch.autograd.Function):
         if _needs(ctx, 2):
             dA = _as(spc.spmm(plan, w, B, transpose=0), A)
         if _needs(ctx, 3):
-            dB = _as(spc.spmm(plan, w, A, transpose=1), B)
+            dB = _as(_spmm_t(plan, w, A), B)
         return None, dvals, dA, dB
 
 
@@ -97,8 +108,11 @@ class SpMMFn(torch.autograd.Function):
             else:
                 dvals = spc.sddmm(plan, None, X, dYx)
         if _needs(ctx, 2):
-            dX = _as(spc.spmm(plan, vals if ctx.has_vals else None, dYx,
-                              transpose=1 - ctx.transpose), X)
+            v = vals if ctx.has_vals else None
+            if ctx.transpose == 0:
+                dX = _as(_spmm_t(plan, v, dYx), X)
+            else:
+                dX = _as(spc.spmm(plan, v, dYx, transpose=0), X)
         return None, dvals, dX, None
 
 
@@ -177,9 +191,9 @@ class FusedAttentionFn(torch.autograd.Function):
         if _needs(ctx, 1):
             dQ = _as(spc.spmm(plan, de, Kf, transpose=0), Q)
         if _needs(ctx, 2):
-            dK = _as(spc.spmm(plan, de, Q, transpose=1), Kf)
+            dK = _as(_spmm_t(plan, de, Q), Kf)
         if _needs(ctx, 3):
-            dV = _as(spc.spmm(plan, alpha, dout, transpose=1), V)
+            dV = _as(_spmm_t(plan, alpha, dout), V)
         return None, dQ, dK, dV
 
 

@@ -47,7 +47,8 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
   const int64_t nblocks = (nitems + 3) / 4;
-  const Orient o = transpose ? p->csc() : p->csr();
+  Orient o = transpose ? p->csc() : p->csr();
+  if (transpose == 2) o.vidx = nullptr;   // values already in column-major slot order
   float* carry = static_cast<float*>(d_buf);
 #define SPC3D_RUN(T, V)                                                                        \
   do {                                                                                         \
@@ -197,7 +198,7 @@ spc3d_status spc3d_spmm(spc3d_plan h, int transpose, const float* d_vals, const 
   Plan* p;
   spc3d_status st = get_plan(h, &p);
   if (st != SPC3D_OK) return st;
-  if (transpose != 0 && transpose != 1) return fail(SPC3D_ERR_INVALID_ARG, "bad transpose");
+  if (transpose < 0 || transpose > 2) return fail(SPC3D_ERR_INVALID_ARG, "bad transpose");
   if (transpose && !(p->flags & SPC3D_BUILD_CSC))
     return fail(SPC3D_ERR_INVALID_ARG, "transposed SpMM needs a plan built with BUILD_CSC");
   if (x_t != SPC3D_F32 && x_t != SPC3D_BF16) return fail(SPC3D_ERR_INVALID_ARG, "bad x_t");

@@ -450,11 +450,14 @@ __global__ void k_group_offsets(int32_t ngroups, int64_t n, const uint64_t* __re
   }
 }
 
-__global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, int dir,
+// gather (out[p] = in[perm[p]]) or scatter (out[perm[p]] = in[p]) of one
+// value per entry; perm is the plan's slot -> caller map, or its column-major
+// slot -> row-major slot map.
+__global__ void k_permute(int64_t nnz, const int32_t* __restrict__ perm, int gather,
                           const float* __restrict__ in, float* __restrict__ out) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
        p += (int64_t)gridDim.x * blockDim.x) {
-    if (dir == SPC3D_CALLER_TO_SLOT)
+    if (gather)
       out[p] = in[perm[p]];
     else
       out[perm[p]] = in[p];
@@ -899,16 +902,20 @@ spc3d_status spc3d_permute_values(spc3d_plan h, int direction, const float* d_in
   Plan* p;
   spc3d_status st = get_plan(h, &p);
   if (st != SPC3D_OK) return st;
-  if (direction != SPC3D_CALLER_TO_SLOT && direction != SPC3D_SLOT_TO_CALLER)
+  if (direction < SPC3D_CALLER_TO_SLOT || direction > SPC3D_COLUMN_TO_SLOT)
     return fail(SPC3D_ERR_INVALID_ARG, "bad direction %d", direction);
+  const bool csc = direction == SPC3D_SLOT_TO_COLUMN || direction == SPC3D_COLUMN_TO_SLOT;
+  if (csc && !(p->flags & SPC3D_BUILD_CSC))
+    return fail(SPC3D_ERR_INVALID_ARG, "column-major order needs a plan built with BUILD_CSC");
   if (p->nnz == 0) return SPC3D_OK;
   if (!d_in || !d_out) return fail(SPC3D_ERR_INVALID_ARG, "NULL array");
   if (d_in == d_out) return fail(SPC3D_ERR_INVALID_ARG, "in and out alias");
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  const int gather = direction == SPC3D_CALLER_TO_SLOT || direction == SPC3D_SLOT_TO_COLUMN;
   hipLaunchKernelGGL(k_permute, dim3(grid_for(p->nnz, 256)), dim3(256), 0, stream, p->nnz,
-                     p->perm, direction, d_in, d_out);
+                     csc ? p->slot_t : p->perm, gather, d_in, d_out);
   SPC3D_LAUNCHED("permute_values");
   return SPC3D_OK;
 }

@@ -21,7 +21,7 @@ F32, BF16 = 0, 1
 ROWS, COLS = 0, 1
 OVERWRITE, ACCUMULATE = 0, 1
 BUILD_CSC = 1
-CALLER_TO_SLOT, SLOT_TO_CALLER = 0, 1
+CALLER_TO_SLOT, SLOT_TO_CALLER, SLOT_TO_COLUMN, COLUMN_TO_SLOT = 0, 1, 2, 3
 OP_SDDMM, OP_SPMM, OP_SDDMM_SPMM = 0, 1, 2
 NFEAT = 23
 FEATURES_BUFFER_BYTES = 256
@@ -320,7 +320,7 @@ def spmm(plan: Plan, vals, X: torch.Tensor, transpose: int = 0, kz: int | None =
          out: torch.Tensor | None = None, mode: int = OVERWRITE, variant: int = -1,
          buf: torch.Tensor | None = None, stream=None):
     kz = X.shape[1] if kz is None else kz
-    n = plan.C if transpose else plan.R
+    n = plan.C if transpose else plan.R      # transpose 1 or 2: over columns
     nx = plan.R if transpose else plan.C
     _need(X.is_contiguous() and X.numel() >= nx * kz, "X too small for kz")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),

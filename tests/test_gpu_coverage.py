@@ -324,3 +324,45 @@ def test_fp32_misaligned_operand_with_sized_buffer():
     fo, fy = spc.sddmm_spmm(plan, v, A, B, kz, buf=buf)
     assert_within_mag(_np(fo), o, mo, what="misaligned fused sddmm")
     assert_within_mag(_np(fy), y, my, what="misaligned fused spmm")
+
+
+# ------------------------------------------- column-major value order
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_transposed_spmm_with_column_major_values(dt):
+    """spc3d_permute_values SLOT_TO_COLUMN / COLUMN_TO_SLOT against the plan's
+    slot map on the host (bit-exact), and the transposed SpMM reading values
+    in column-major order (transpose 2) bit for bit equal to the one reading
+    them through the slot map (transpose 1), for every SpMM family; both
+    within 1e-5 M of the oracle."""
+    spc = _spc()
+    p = synth.small_rmat(12, 8, 32, 57, row_range=(1 << 11, 1 << 12), col_range=(0, 1 << 11))
+    kz = 32
+    ref = oracle.relabel(p.rows, p.cols, p.row_range, p.col_range, csc=True)
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    v = torch.from_numpy(p.vals[ref["perm"]]).to(DEV)
+    vt = spc.permute_values(plan, spc.SLOT_TO_COLUMN, v)
+    np.testing.assert_array_equal(_np(vt), p.vals[ref["perm"]][ref["slot_t"]])
+    back = spc.permute_values(plan, spc.COLUMN_TO_SLOT, vt)
+    assert torch.equal(back, v)
+    tdt = torch.float32 if dt == "f32" else torch.bfloat16
+    A = spc.gather(plan, spc.ROWS, torch.from_numpy(p.A_src).to(DEV), 0, kz, tdt)
+    Aref = p.A_src if dt == "f32" else _bf16_round(p.A_src)
+    yt, myt = oracle.spmm(p.cols, p.rows, p.col_range[0], p.row_range[0], ref["lmap_c"], ref["C"],
+                          p.vals, Aref, 0, kz)
+    for var in (-1, (3, 2), (2, 3, 1), (3, 0, 0, 1), (1, 2, 0, 1)):
+        vv = var if isinstance(var, int) else spc.variant(*var)
+        y1 = spc.spmm(plan, v, A, 1, kz, variant=vv)
+        y2 = spc.spmm(plan, vt, A, 2, kz, variant=vv)
+        assert torch.equal(y1.view(torch.int32), y2.view(torch.int32)), var
+        assert_within_mag(_np(y2), yt, myt, what=f"spmm transpose 2 {dt} v={var}")
+    # a plan without the column-major view refuses both
+    plain = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV),
+                                torch.from_numpy(p.cols).to(DEV), p.row_range, p.col_range)
+    for call in (lambda: spc.permute_values(plain, spc.SLOT_TO_COLUMN, v),
+                 lambda: spc.spmm(plain, vt, A, 2, kz),
+                 lambda: spc.permute_values(plan, 4, v)):
+        with pytest.raises(spc.Spc3dError) as e:
+            call()
+        assert e.value.status == spc.ERR_INVALID_ARG
