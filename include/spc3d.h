@@ -464,9 +464,14 @@ spc3d_status spc3d_mlp_adam(int64_t n, float* d_w, const float* d_g, float* d_m,
                             hipStream_t stream);
 
 /* idx[r] = the least-P column o among those with mask[r*m + o] != 0 (the
- * first on ties), -1 when a row has none; P and mask [n x m] FP32. */
+ * first on ties), -1 when a row has none; P and mask [n x m] FP32.  With
+ * 0 <= pref < m, idx[r] = pref instead when pref is allowed in row r and
+ * P[r*m + pref] <= P[r*m + o] + margin (an FP32 sum): a preferred column
+ * (the selector's default shape) kept unless another is predicted better by
+ * more than margin.  pref = -1 for none; margin finite and >= 0. */
 spc3d_status spc3d_mlp_masked_argmin(int n, int m, const float* d_P, const float* d_mask,
-                                     int32_t* d_idx, hipStream_t stream);
+                                     int32_t pref, float margin, int32_t* d_idx,
+                                     hipStream_t stream);
 
 /* ----------------------------------------------------------- diagnostics */
 

@@ -99,9 +99,11 @@ def adam(w, g, m, v, lr, b1, b2, eps, t):
     return np.asarray(w, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def masked_argmin(P, M) -> np.ndarray:
+def masked_argmin(P, M, pref: int = -1, margin: float = 0.0) -> np.ndarray:
     """Per row, the index of the least P among entries with M != 0 (first on
-    ties), -1 for a row with none."""
+    ties), -1 for a row with none.  With pref >= 0: pref instead when M allows
+    it and P[pref] <= least + margin, the sum taken in FP32 as the device
+    takes it (a preference kept unless beaten by more than margin)."""
     P = np.asarray(P)
     M = np.asarray(M)
     out = np.full(P.shape[0], -1, dtype=np.int64)
@@ -110,6 +112,10 @@ def masked_argmin(P, M) -> np.ndarray:
         for o in range(P.shape[1]):
             if M[r, o] != 0 and (best < 0 or P[r, o] < P[r, best]):
                 best = o
+        if best >= 0 and pref >= 0 and M[r, pref] != 0:
+            bound = np.float32(np.float32(P[r, best]) + np.float32(margin))
+            if np.float32(P[r, pref]) <= bound:
+                best = pref
         out[r] = best
     return out
 

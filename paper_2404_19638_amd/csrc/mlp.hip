@@ -189,9 +189,12 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict
 }
 
 // idx[r] = the column o < m with mask[r][o] != 0 and the least P[r][o] (the
-// first such column on ties); -1 when the row's mask is all zero.
+// first such column on ties); -1 when the row's mask is all zero.  With pref
+// in [0, m): pref instead, when it is allowed and P[r][pref] <= least + margin
+// (FP32 sum).
 __global__ void k_masked_argmin(int n, int m, const float* __restrict__ P,
-                                const float* __restrict__ M, int32_t* __restrict__ idx) {
+                                const float* __restrict__ M, int pref, float margin,
+                                int32_t* __restrict__ idx) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   int best = -1;
@@ -204,6 +207,9 @@ __global__ void k_masked_argmin(int n, int m, const float* __restrict__ P,
       bv = v;
     }
   }
+  if (best >= 0 && pref >= 0 && M[(int64_t)r * m + pref] != 0.f &&
+      P[(int64_t)r * m + pref] <= bv + margin)
+    best = pref;
   idx[r] = best;
 }
 
@@ -350,12 +356,16 @@ spc3d_status spc3d_mlp_adam(int64_t n, float* d_w, const float* d_g, float* d_m,
 }
 
 spc3d_status spc3d_mlp_masked_argmin(int n, int m, const float* d_P, const float* d_mask,
-                                     int32_t* d_idx, hipStream_t stream) {
+                                     int32_t pref, float margin, int32_t* d_idx,
+                                     hipStream_t stream) {
   if (n < 0 || m < 1) return fail(SPC3D_ERR_INVALID_ARG, "bad sizes n=%d m=%d", n, m);
+  if (pref < -1 || pref >= m) return fail(SPC3D_ERR_INVALID_ARG, "pref=%d outside [-1,%d)", pref, m);
+  if (!(margin >= 0.f && margin <= 3.4e38f))
+    return fail(SPC3D_ERR_INVALID_ARG, "margin must be finite and >= 0");
   if (n == 0) return SPC3D_OK;
   if (!d_P || !d_mask || !d_idx) return fail(SPC3D_ERR_INVALID_ARG, "NULL buffer");
   hipLaunchKernelGGL(k_masked_argmin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n,
-                     m, d_P, d_mask, d_idx);
+                     m, d_P, d_mask, pref, margin, d_idx);
   SPC3D_LAUNCHED("spc3d_mlp_masked_argmin");
   return SPC3D_OK;
 }

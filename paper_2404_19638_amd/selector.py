@@ -26,6 +26,16 @@ from . import tune
 
 NFEAT = spc.NFEAT
 TARGET_CAP = 3.0  # slowdowns beyond 8x are all "bad"; capping keeps them from dominating the loss
+# The library default (variant -1) is kept unless another candidate is
+# predicted faster by more than this (log2 of 1.03: about the spread of
+# repeated timings of one call).
+KEEP_DEFAULT_MARGIN = math.log2(1.03)
+
+
+def candidates(op: str) -> list:
+    """The network's outputs for op: the library default shape (-1) first,
+    then every explicit variant the autotuner times."""
+    return [-1] + tune.candidates(op)
 
 
 class MLP:
@@ -121,7 +131,7 @@ class MLP:
 
 def valid_mask(op: str, kz: int, dtype: int, cands=None) -> np.ndarray:
     """1.0 for the candidates of op that can run with (kz, dtype), else 0.0."""
-    cands = tune.candidates(op) if cands is None else cands
+    cands = candidates(op) if cands is None else cands
     return np.array([1.0 if tune.valid(op, kz, dtype, v) else 0.0 for v in cands],
                     dtype=np.float32)
 
@@ -129,7 +139,7 @@ def valid_mask(op: str, kz: int, dtype: int, cands=None) -> np.ndarray:
 def targets(timings: dict, op: str, cands=None):
     """Training row of one autotune result: (T, M) over the candidates of op,
     T = min(log2(t_v / t_best), TARGET_CAP) where timed, M = 1 there."""
-    cands = tune.candidates(op) if cands is None else cands
+    cands = candidates(op) if cands is None else cands
     best = min(t for v, t in timings.items() if v in cands)
     T = np.zeros(len(cands), np.float32)
     M = np.zeros(len(cands), np.float32)
@@ -143,8 +153,10 @@ def targets(timings: dict, op: str, cands=None):
 class Selector:
     """One MLP per operation, plus the feature range seen in training."""
 
-    def __init__(self, hidden=(64, 64), seed: int = 7, device="cuda"):
+    def __init__(self, hidden=(64, 64), seed: int = 7, device="cuda",
+                 margin: float = KEEP_DEFAULT_MARGIN):
         self.hidden = tuple(hidden)
+        self.margin = margin
         self.seed = seed
         self.device = torch.device(device)
         self.models = {}
@@ -156,7 +168,7 @@ class Selector:
     def fit(self, op: str, X: np.ndarray, T: np.ndarray, M: np.ndarray, steps: int = 3000,
             lr: float = 3e-3, lr_final: float = 3e-4, log_every: int = 0, log=None) -> list:
         X = np.asarray(X, np.float32)
-        self.cands[op] = tune.candidates(op)
+        self.cands[op] = candidates(op)
         ncand = len(self.cands[op])
         assert X.shape[1] == NFEAT and T.shape[1] == ncand and M.shape == T.shape
         mlp = MLP([NFEAT, *self.hidden, ncand], self.seed + tune.OPCODE[op], self.device)
@@ -178,9 +190,11 @@ class Selector:
 
     def predict_indices(self, op: str, X: torch.Tensor, masks: torch.Tensor) -> torch.Tensor:
         """Per row of X, the index into self.cands[op] of the least
-        predicted slowdown among the allowed ones (device int32, -1 if none)."""
+        predicted slowdown among the allowed ones (device int32, -1 if none);
+        the default shape is kept unless beaten by more than self.margin."""
         P = self.models[op].predict(X)
-        return spc.mlp_masked_argmin(P, masks.contiguous())
+        pref = self.cands[op].index(-1) if -1 in self.cands[op] else -1
+        return spc.mlp_masked_argmin(P, masks.contiguous(), pref=pref, margin=self.margin)
 
     def in_range(self, op: str, f: np.ndarray, margin: float = 0.05) -> bool:
         """True when every feature lies within the training range (+- margin)."""
@@ -259,7 +273,8 @@ def collect(blocks, ks=(16, 32, 64, 128), dtypes=(spc.F32, spc.BF16), ops=tune.O
 
 
 def dataset(recs: list, op: str, cands=None):
-    """(X, T, M) arrays of the records of op over its candidates."""
+    """(X, T, M) arrays of the records of op over its candidates (the
+    network's outputs, candidates(op), unless given)."""
     rs = [r for r in recs if r["op"] == op]
     X = np.stack([r["features"] for r in rs]).astype(np.float32)
     TM = [targets(r["timings"], op, cands) for r in rs]
@@ -387,6 +402,39 @@ def load_records(path: str) -> list:
                  timings={int(k): v for k, v in r["timings"].items()}) for r in rows]
 
 
+def save_records_npz(recs: list, path: str):
+    """Records as compact arrays (one row per record, one timing column per
+    variant of candidates("spmm"), NaN where a variant was not timed)."""
+    cols = candidates("spmm")
+    col = {v: i for i, v in enumerate(cols)}
+    T = np.full((len(recs), len(cols)), np.nan, np.float32)
+    for i, r in enumerate(recs):
+        for v, t in r["timings"].items():
+            T[i, col[v]] = t
+    np.savez_compressed(path, variants=np.array(cols, np.int32), timings=T,
+                        features=np.stack([r["features"] for r in recs]).astype(np.float32),
+                        block=np.array([r["block"] for r in recs], np.int32),
+                        kz=np.array([r["kz"] for r in recs], np.int32),
+                        dtype=np.array([r["dtype"] for r in recs], np.int32),
+                        op=np.array([r["op"] for r in recs]),
+                        nnz=np.array([r["nnz"] for r in recs], np.int64),
+                        kind=np.array([r["kind"] for r in recs]), n=np.array([r["n"] for r in recs]))
+
+
+def load_records_npz(path: str) -> list:
+    z = np.load(path, allow_pickle=False)
+    cols = [int(v) for v in z["variants"]]
+    out = []
+    for i in range(z["timings"].shape[0]):
+        row = z["timings"][i]
+        out.append(dict(block=int(z["block"][i]), kind=str(z["kind"][i]), n=int(z["n"][i]),
+                        nnz=int(z["nnz"][i]), kz=int(z["kz"][i]), dtype=int(z["dtype"][i]),
+                        op=str(z["op"][i]), features=z["features"][i],
+                        timings={v: float(row[k]) for k, v in enumerate(cols)
+                                 if not np.isnan(row[k])}))
+    return out
+
+
 def main(argv=None):
     """Collect autotuner timings on the selector workload, train one MLP per
     operation on the training blocks, and judge it on the held-out blocks."""
@@ -409,6 +457,7 @@ def main(argv=None):
     ap.add_argument("--save-data", help="write the autotuner records to this JSON")
     ap.add_argument("--out", help="write the report and the trained networks to this JSON")
     ap.add_argument("--weights", help="write the trained networks (compact) to this JSON")
+    ap.add_argument("--save-heldout", help="write the held-out blocks' records (compact .npz)")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -443,6 +492,8 @@ def main(argv=None):
     train, held = set(train) & timed, set(held) & timed
     rtrain = [r for r in recs if r["block"] in train]
     rheld = [r for r in recs if r["block"] in held]
+    if args.save_heldout:
+        save_records_npz(rheld, args.save_heldout)
     sel = Selector(args.hidden)
     report = dict(blocks=len(timed), train_blocks=len(train), held_out_blocks=len(held),
                   steps=args.steps, hidden=args.hidden, reps=args.reps, ops={})

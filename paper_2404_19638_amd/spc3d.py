@@ -98,7 +98,8 @@ def lib():
                                 + [sz, vp],
         "spc3d_mlp_mse": [i64, vp, vp, vp, vp, vp, vp],
         "spc3d_mlp_adam": [i64, vp, vp, vp, vp] + [ctypes.c_float] * 4 + [ctypes.c_int, vp],
-        "spc3d_mlp_masked_argmin": [ctypes.c_int, ctypes.c_int, vp, vp, vp, vp],
+        "spc3d_mlp_masked_argmin": [ctypes.c_int, ctypes.c_int, vp, vp, i32, ctypes.c_float, vp,
+                                    vp],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -681,11 +682,14 @@ def mlp_adam(w, g, m, v, lr: float, beta1: float, beta2: float, eps: float, step
     return w
 
 
-def mlp_masked_argmin(P, M, out=None, stream=None):
+def mlp_masked_argmin(P, M, pref: int = -1, margin: float = 0.0, out=None, stream=None):
+    """Per row the least-P allowed column, or pref when it is allowed and within
+    margin of that least value (spc3d_mlp_masked_argmin)."""
     n, m = P.shape
     _f32_2d(P, n, m, "P")
     _f32_2d(M, n, m, "M")
     out = torch.empty(n, dtype=torch.int32, device=P.device) if out is None else out
-    _check(lib().spc3d_mlp_masked_argmin(n, m, _ptr(P), _ptr(M), _ptr(out), _stream(stream)),
+    _check(lib().spc3d_mlp_masked_argmin(n, m, _ptr(P), _ptr(M), pref, margin, _ptr(out),
+                                         _stream(stream)),
            "spc3d_mlp_masked_argmin")
     return out

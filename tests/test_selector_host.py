@@ -16,21 +16,25 @@ def test_candidates_and_masks():
     assert len(sd) == len(set(sd)) and len(sp) == len(set(sp))
     assert all(not (v >> 8) & 3 for v in sd)          # SDDMM ignores the SpMM bits
     assert set(sd) < set(sp) and tune.candidates("sddmm_spmm") == sp
+    # the network's outputs: the library default (-1) first, then every variant
+    assert S.candidates("spmm") == [-1] + sp and S.candidates("sddmm") == [-1] + sd
     m = S.valid_mask("spmm", 32, spc.F32)
-    assert m.shape == (len(sp),) and set(np.unique(m)) <= {0.0, 1.0}
-    for v, ok in zip(sp, m):
+    assert m.shape == (len(sp) + 1,) and set(np.unique(m)) <= {0.0, 1.0} and m[0] == 1.0
+    for v, ok in zip(S.candidates("spmm"), m):
         assert bool(ok) == (spc.variant_check(spc.OP_SPMM, 32, spc.F32, v) == spc.OK)
     # kz = 128 FP32 needs at least 8 lanes per entry
     m128 = S.valid_mask("sddmm", 128, spc.F32)
-    assert all(not ok for v, ok in zip(sd, m128) if (v & 15) < 3)
+    assert all(not ok for v, ok in zip(S.candidates("sddmm"), m128) if v >= 0 and (v & 15) < 3)
 
 
 def test_targets_are_capped_log_slowdowns():
-    c = tune.candidates("sddmm")
-    t = {c[0]: 1.0, c[1]: 2.0, c[2]: 100.0, -1: 1.5}
+    c = S.candidates("sddmm")
+    assert c[0] == -1
+    t = {c[1]: 1.0, c[2]: 2.0, c[3]: 100.0, -1: 1.5}
     T, M = S.targets(t, "sddmm")
-    assert T[0] == 0.0 and T[1] == 1.0 and T[2] == S.TARGET_CAP
-    assert M[:3].tolist() == [1, 1, 1] and M[3:].sum() == 0 and T[3:].sum() == 0
+    assert T[1] == 0.0 and T[2] == 1.0 and T[3] == S.TARGET_CAP
+    assert T[0] == math.log2(1.5)
+    assert M[:4].tolist() == [1, 1, 1, 1] and M[4:].sum() == 0 and T[4:].sum() == 0
 
 
 def _rec(op, timings, block=0):

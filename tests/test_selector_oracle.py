@@ -168,3 +168,29 @@ def test_masked_argmin_brute_force():
     want = np.where(M.any(axis=1), np.argmin(masked, axis=1), -1)  # argmin: first minimum
     np.testing.assert_array_equal(got, want)
     assert got[7] == -1
+
+
+def test_masked_argmin_preferred_column():
+    """The preferred column is kept while within margin of the least allowed
+    value, and only then; hand cases, then brute force."""
+    P = np.array([[1.0, 0.5, 0.49], [1.0, 0.5, 0.4], [1.0, 0.5, 0.4], [2.0, 0.5, 9.0]],
+                 np.float32)
+    M = np.array([[1, 1, 1], [1, 1, 1], [0, 1, 1], [1, 1, 1]], np.float32)
+    # pref 1: within 0.05 of 0.49 -> 1; 0.1 above 0.4 -> 2; pref 0 masked off
+    np.testing.assert_array_equal(mlp.masked_argmin(P[:2], M[:2], pref=1, margin=0.05), [1, 2])
+    np.testing.assert_array_equal(mlp.masked_argmin(P[2:3], M[2:3], pref=0, margin=5.0), [2])
+    np.testing.assert_array_equal(mlp.masked_argmin(P[3:], M[3:], pref=0, margin=1.5), [0])
+    np.testing.assert_array_equal(mlp.masked_argmin(P[3:], M[3:], pref=0, margin=1.4), [1])
+    rng = np.random.default_rng(5)
+    P = rng.integers(0, 8, (300, 7)).astype(np.float32) / 4
+    M = (rng.random((300, 7)) < 0.7).astype(np.float32)
+    for pref, margin in ((0, 0.0), (3, 0.25), (6, 1.0)):
+        got = mlp.masked_argmin(P, M, pref=pref, margin=margin)
+        base = mlp.masked_argmin(P, M)
+        for r in range(300):
+            if base[r] < 0:
+                assert got[r] == -1
+            elif M[r, pref] and P[r, pref] <= P[r, base[r]] + margin:
+                assert got[r] == pref
+            else:
+                assert got[r] == base[r]
