@@ -6,6 +6,9 @@
  * against the FP64 oracle's C functions (liboracle.so, test infrastructure):
  * the maps, CSR arrays, packed rows and the scatter-reduce bit for bit, the
  * SDDMM and SpMM values within 1e-5 of the magnitude sum of their terms.
+ * The same pass with the scatter-reduce folded in must leave the slab bit for
+ * bit as the separate scatter-reduce did, and the entry point without a
+ * buffer argument must reproduce the buffered pass bit for bit.
  * It also exercises three error paths (an id outside the block's range, a
  * bad argument, a destroyed plan).  Exit status 0 and the line
  * "abi_client: ok" mean every check passed.
@@ -111,6 +114,8 @@ int main(void) {
   for (int64_t i = 0; i < nr * K; ++i) A_src[i] = next_unit(&seed);
   for (int64_t i = 0; i < nc * K; ++i) B_src[i] = next_unit(&seed);
   for (int64_t i = 0; i < nr * K; ++i) Y_dst[i] = next_unit(&seed);
+  float* Y_dst0 = malloc(sizeof(float) * nr * K);   /* the slab before the step */
+  memcpy(Y_dst0, Y_dst, sizeof(float) * nr * K);
 
   /* the oracle */
   int64_t R = 0, C = 0;
@@ -233,6 +238,33 @@ int main(void) {
   /* scatter-reduce of the GPU's own Y: bit for bit, untouched rows unchanged */
   oracle_scatter_add_f32(R, o_gmap_r, row_lo, Y, kz, Y_dst, K, k0);
   EXPECT(!memcmp(Y_after, Y_dst, sizeof(float) * nr * K), "scatter-reduce");
+
+  /* the scatter-reduce folded into the pass, on a fresh copy of the slab:
+   * the same row sums added in the same order, so the same bits */
+  float *d_Y_dst2 = dev_copy(Y_dst0, sizeof(float) * nr * K), *d_out2 = NULL;
+  EXPECT(d_Y_dst2, "second slab");
+  HIPCHECK(hipMalloc((void**)&d_out2, sizeof(float) * nnz));
+  CHECK(spc3d_sddmm_spmm_scatter(plan, d_vals, d_A, d_B, SPC3D_F32, kz, d_out2, SPC3D_OVERWRITE,
+                                 d_Y_dst2, K, k0, -1, d_buf, buf_bytes, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  float* out2 = malloc(sizeof(float) * nnz);
+  HIPCHECK(hipMemcpy(out2, d_out2, sizeof(float) * nnz, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(Y_after, d_Y_dst2, sizeof(float) * nr * K, hipMemcpyDeviceToHost));
+  EXPECT(!memcmp(out2, out, sizeof(float) * nnz), "folded pass: SDDMM values");
+  EXPECT(!memcmp(Y_after, Y_dst, sizeof(float) * nr * K), "folded pass: slab");
+
+  /* the entry point that allocates nothing and takes no buffer */
+  float* d_Y2 = NULL;
+  HIPCHECK(hipMalloc((void**)&d_Y2, sizeof(float) * R * kz));
+  CHECK(spc3d_sddmm_spmm_static(plan, d_vals, d_A, d_B, SPC3D_F32, kz, d_out2, d_Y2,
+                                SPC3D_OVERWRITE, -1, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  float* Y2 = malloc(sizeof(float) * R * kz);
+  HIPCHECK(hipMemcpy(out2, d_out2, sizeof(float) * nnz, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(Y2, d_Y2, sizeof(float) * R * kz, hipMemcpyDeviceToHost));
+  EXPECT(!memcmp(out2, out, sizeof(float) * nnz), "no-buffer pass: SDDMM values");
+  EXPECT(!memcmp(Y2, Y, sizeof(float) * R * kz), "no-buffer pass: SpMM rows");
+  hipFree(d_Y_dst2); hipFree(d_out2); hipFree(d_Y2);
 
   /* error paths */
   EXPECT(spc3d_gather(plan, SPC3D_ROWS, d_A_src, SPC3D_F32, K, k0, 0, d_A, SPC3D_F32, st) ==

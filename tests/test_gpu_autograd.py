@@ -262,6 +262,14 @@ def test_attention_workload_full_size():
         torch.cuda.synchronize()
         b_f += t1 - t0
         b_b += time.perf_counter() - t1
+    with torch.no_grad():
+        ag.gnn_attention(plan, bq, bk, bv, fused=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ag.gnn_attention(plan, bq, bk, bv, fused=True)
+        torch.cuda.synchronize()
+        b_fused = (time.perf_counter() - t0) / reps
     flops = 2 * 2 * K * p.nnz
     print("ATTENTION_REPORT " + json.dumps({
         "workload": "rmat20-deg32-whole-K64", "nnz": p.nnz, "R": R, "C": C,
@@ -269,6 +277,7 @@ def test_attention_workload_full_size():
         "forward_ms": round(t_f / reps * 1e3, 3), "backward_ms": round(t_b / reps * 1e3, 3),
         "forward_ms_fused_no_grad": round(t_fused * 1e3, 3),
         "bf16_forward_ms": round(b_f / reps * 1e3, 3), "bf16_backward_ms": round(b_b / reps * 1e3, 3),
+        "bf16_forward_ms_fused_no_grad": round(b_fused * 1e3, 3),
         "forward_sddmm_spmm_GFLOPs": round(flops / (t_f / reps) / 1e9, 1)}), flush=True)
 
 
@@ -328,3 +337,54 @@ def test_bf16_attention_training_against_fp32_on_rounded_inputs(fused):
         err = np.abs(gb - want)
         _say(f"  {name} vs oracle: max err/bound {float((err / bound).max()):.3f}")
         assert (err <= bound).all(), (name, int((err > bound).sum()))
+
+
+def test_column_sliced_inputs_in_forward_and_backward():
+    """Operands that are column blocks of wider tensors (not contiguous): the
+    functions pack them once and keep the packed copies for the backward, so
+    the forward equals that of the same values given contiguous bit for bit,
+    and the gradients up to the order in which autograd adds the
+    contributions of an operand's several uses (SDDMM and SpMM with values,
+    and the attention layer)."""
+    spc, ag = _mods()
+    p = synth.small_rmat(11, 8, 16, 97, row_range=(1 << 10, 1 << 11), col_range=(0, 1 << 10))
+    plan = spc.plan_create_coo(torch.from_numpy(p.rows).to(DEV), torch.from_numpy(p.cols).to(DEV),
+                               p.row_range, p.col_range, spc.BUILD_CSC)
+    R, C, K = plan.R, plan.C, 16
+    _say(f"column-sliced operands nnz={plan.nnz}")
+    wide_r = torch.from_numpy(synth.dense_f32(601, 0, R, 3 * K)).to(DEV)
+    wide_c = torch.from_numpy(synth.dense_f32(602, 0, C, 3 * K)).to(DEV)
+    vals = torch.from_numpy(synth.uniform_f32(603, plan.nnz)).to(DEV)
+    G1 = torch.from_numpy(synth.uniform_f32(604, plan.nnz)).to(DEV)
+    G2 = torch.from_numpy(synth.dense_f32(605, 0, R, K)).to(DEV)
+
+    def run(sliced):
+        if sliced:
+            wr = wide_r.clone().requires_grad_()
+            wc = wide_c.clone().requires_grad_()
+            A, B, V = wr[:, K:2 * K], wc[:, :K], wc[:, 2 * K:]
+            assert not (A.is_contiguous() or B.is_contiguous() or V.is_contiguous())
+            leaves = (wr, wc)
+        else:
+            A = wide_r[:, K:2 * K].contiguous().requires_grad_()
+            B = wide_c[:, :K].contiguous().requires_grad_()
+            V = wide_c[:, 2 * K:].contiguous().requires_grad_()
+            leaves = (A, B, V)
+        v = vals.clone().requires_grad_()
+        c = ag.sddmm(plan, v, A, B)
+        y = ag.spmm(plan, v, B, 0)
+        att = ag.gnn_attention(plan, A, B, V)
+        ((c * G1).sum() + (y * G2).sum() + (att * G2).sum()).backward()
+        if sliced:
+            gr, gc = leaves[0].grad, leaves[1].grad
+            grads = (gr[:, K:2 * K], gc[:, :K], gc[:, 2 * K:])
+        else:
+            grads = tuple(t.grad for t in leaves)
+        return [c.detach(), y.detach(), att.detach(), v.grad, *grads]
+
+    got, want = run(True), run(False)
+    for a, b in zip(got[:3], want[:3]):
+        assert torch.equal(a.contiguous().view(torch.int32), b.contiguous().view(torch.int32))
+    for a, b in zip(got[3:], want[3:]):
+        scale = b.abs().max().item()
+        assert (a - b).abs().max().item() <= 1e-6 * scale, (a - b).abs().max().item()
