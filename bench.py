@@ -151,17 +151,24 @@ def copy_bandwidth(dev, mib=1024, reps=10):
     return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
-def cold_steps(step, names, spans, nev, alg, steps, dev, flops):
+def cold_steps(step, names, spans, nev, alg, steps, dev, flops, dirty=False):
     """The step and each kernel with L2 and the Infinity Cache flushed before
-    every step by a 1 GiB write (the flush is outside the events, which
-    bracket the step from its first kernel to its last)."""
+    every step (the flush is outside the events, which bracket the step from
+    its first kernel to its last).  The flush writes 1 GiB, which evicts the
+    step's lines, then reads it back, so that the cache holds clean lines
+    and the step does not also pay for writing the flush's dirty lines back
+    to HBM.  dirty=True leaves out the read: the step then runs against a
+    cache full of dirty lines."""
     import numpy as np
     import torch
 
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    sink = torch.empty(1, dtype=torch.float32, device=dev)
     evs = []
     for i in range(steps):
         flush.fill_(float(i))
+        if not dirty:
+            torch.sum(flush, 0, keepdim=True, out=sink)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(nev)]
         step(ev)
         evs.append(ev)
@@ -176,7 +183,8 @@ def cold_steps(step, names, spans, nev, alg, steps, dev, flops):
     total = sum(alg[n] for n in names)
     dom = max(names, key=lambda n: kernels[n]["ms"])
     del flush
-    return {"steps": steps, "step_ms": round(step_ms, 5),
+    return {"steps": steps, "flush": "1 GiB write" if dirty else "1 GiB write, then read",
+            "step_ms": round(step_ms, 5),
             "value": round(flops / (step_ms * 1e-3) / 1e9, 2),
             "step_frac_hbm": round(total / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"],
@@ -238,7 +246,7 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cold-steps", type=int, default=10,
-                    help="extra steps, each after a 1 GiB flush write, for cold-cache kernel times")
+                    help="extra steps, each after a 1 GiB flush, for cold-cache step and kernel times")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the BF16 and learned-selector forms")
     ap.add_argument("--seed", type=int, default=2405)
@@ -517,6 +525,11 @@ def main():
     if args.cold_steps:
         res["cold"] = cold_steps(make_step(args.dtype, args.variant), names, spans, nev, alg,
                                  args.cold_steps, dev, flops)
+        d = cold_steps(make_step(args.dtype, args.variant), names, spans, nev, alg,
+                       args.cold_steps, dev, flops, dirty=True)
+        res["cold"]["dirty_flush"] = {"flush": d["flush"], "step_ms": d["step_ms"],
+                                      "value": d["value"],
+                                      "kernels_ms": {n: d["kernels"][n]["ms"] for n in names}}
     if not args.no_forms:
         res["forms"] = forms(args, spc, plan, kz, nnz, make_step, timed, names, eager_ms,
                              per_kernel_ms, flops)

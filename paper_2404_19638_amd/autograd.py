@@ -225,17 +225,47 @@ def _need_fused(Q, Kf, V):
         raise ValueError("the fused attention pass needs 16-byte aligned Q, Kf and V")
 
 
-def gnn_attention(plan, Q, Kf, V, fused: bool = False):
+# Largest FP32 block (stored entries) on which the automatic choice takes the
+# one-pass forward: it measured faster at 1.8M entries (R-MAT 2^16, K = 64) and
+# slower from 7.6M entries (2^18) on, where the Kf and V rows it keeps live
+# together outgrow the Infinity Cache.  With bfloat16 operands it measured
+# faster at every size up to 31.4M entries (2^20).
+AUTO_FUSED_F32_MAX_NNZ = 1 << 21
+
+
+def _auto_fused(plan, Q, Kf, V):
+    """The forward gnn_attention takes when the caller leaves it open: the
+    one-pass kernel for inference (no gradient is recorded) where it measured
+    faster, the three kernels otherwise (the fused backward recomputes the
+    scores, and the fused forward loses in FP32 on large blocks)."""
+    if torch.is_grad_enabled() and any(t.requires_grad for t in (Q, Kf, V)):
+        return False
+    if not (Q.dtype == Kf.dtype == V.dtype) or Q.dtype not in (torch.float32, torch.bfloat16):
+        return False
+    dt = spc.BF16 if Q.dtype == torch.bfloat16 else spc.F32
+    if not spc.attention_supported(Q.shape[1], dt):
+        return False
+    if not all(t.is_contiguous() and t.data_ptr() % 16 == 0 for t in (Q, Kf, V)):
+        return False
+    return dt == spc.BF16 or plan.nnz <= AUTO_FUSED_F32_MAX_NNZ
+
+
+def gnn_attention(plan, Q, Kf, V, fused: bool | None = None):
     """Masked attention over the block's pattern: SDDMM edge scores (s == 1),
     row softmax over each row's stored entries, SpMM aggregation of V.
 
     Q is [R, K] (local rows), Kf and V are [C, K] (local columns); returns [R, K].
     fused=True runs the forward as one pass (spc3d_attention_fwd; K must be
     covered by it, see spc.attention_supported) and recomputes the scores in
-    the backward.  The default is the three separate kernels: on MI355X the
-    layer is bound by the gathers of Kf and V rows, which the fused pass keeps
-    live together, and it measured no faster in FP32 beyond 2^16 vertices.
+    the backward; fused=False runs the three separate kernels.  Left as None,
+    the one-pass forward is taken for inference (no gradient recorded) with
+    bfloat16 operands, or FP32 operands on blocks of up to
+    AUTO_FUSED_F32_MAX_NNZ entries, and the three kernels otherwise: the
+    layer is bound by the gathers of Kf and V rows, which the fused pass
+    keeps live together, so in FP32 it measured slower on large blocks.
     """
+    if fused is None:
+        fused = _auto_fused(plan, Q, Kf, V)
     if fused:
         _need_fused(Q, Kf, V)
         return FusedAttentionFn.apply(plan, Q, Kf, V)

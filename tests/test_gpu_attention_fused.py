@@ -165,6 +165,32 @@ def test_fused_attention_matches_unfused_layer_and_rejects_uncovered_shapes():
             spc.attention_fwd(plan, q, k, k, bad_kz)
 
 
+def test_automatic_forward_choice_runs_the_chosen_kernels():
+    """gnn_attention with fused left open: for inference with bfloat16 (and
+    small FP32) operands its output is the one-pass kernel's, bit for bit;
+    with a gradient to record it is the three kernels'."""
+    spc = _spc()
+    from paper_2404_19638_amd import autograd as ag
+    name, rows, cols, n = _patterns()[0]
+    plan = spc.plan_create_coo(torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV),
+                               (0, n), (0, n), spc.BUILD_CSC)
+    _say(f"automatic attention forward {name} nnz={plan.nnz}")
+    kz = 32
+    for dt in (torch.bfloat16, torch.float32):
+        tq, tk, tv = (torch.from_numpy(synth.dense_f32(s, 0, m, kz)).to(DEV).to(dt)
+                      for s, m in ((94, plan.R), (95, plan.C), (96, plan.C)))
+        with torch.no_grad():
+            auto = ag.gnn_attention(plan, tq, tk, tv)
+            one = ag.gnn_attention(plan, tq, tk, tv, fused=True)
+            three = ag.gnn_attention(plan, tq, tk, tv, fused=False)
+        assert torch.equal(auto.view(torch.int16 if dt == torch.bfloat16 else torch.int32),
+                           one.view(torch.int16 if dt == torch.bfloat16 else torch.int32))
+        tqg = tq.clone().requires_grad_()
+        auto_g = ag.gnn_attention(plan, tqg, tk, tv)
+        assert torch.equal(auto_g.detach().view(torch.int16 if dt == torch.bfloat16 else torch.int32),
+                           three.view(torch.int16 if dt == torch.bfloat16 else torch.int32))
+
+
 def test_row_softmax_and_backward_against_oracle():
     """The separate softmax kernels (forward and backward) on the same patterns,
     with 16-byte aligned arrays and with arrays offset by one float (the
