@@ -268,7 +268,7 @@ spc3d_status spc3d_sddmm_spmm_scatter(spc3d_plan plan, const float* d_vals, cons
 
 /* Bytes of the library's static scratch array (one per GPU) that
  * spc3d_sddmm_spmm_static uses in place of a caller buffer. */
-#define SPC3D_STATIC_SCRATCH_BYTES (8u << 20)
+#define SPC3D_STATIC_SCRATCH_BYTES (16u << 20)
 
 /* spc3d_sddmm_spmm for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
@@ -280,7 +280,7 @@ spc3d_status spc3d_sddmm_spmm_scatter(spc3d_plan plan, const float* d_vals, cons
  * behind: calls that overlap on one GPU (on different streams, or from
  * different threads) race and must be ordered by the caller.  A call whose
  * carries need more than SPC3D_STATIC_SCRATCH_BYTES (2 * kz * 4 bytes per
- * work item; e.g. 8 MiB covers 4M entries at kz = 128 in the default shape)
+ * work item; e.g. 16 MiB covers 4M entries at kz = 128 in the default shape)
  * returns SPC3D_ERR_WORKSPACE before any launch.  Other errors as for
  * spc3d_sddmm_spmm. */
 spc3d_status spc3d_sddmm_spmm_static(spc3d_plan plan, const float* d_vals, const void* d_A,

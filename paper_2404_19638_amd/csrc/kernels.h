@@ -870,9 +870,11 @@ inline int pow2ceil(int n) {
 // nnz / 4096 slots clamped to [64, 512] so that small blocks still launch
 // enough wavefronts, in the windowed family below 2^18 entries and in the
 // group-run family above.  The fused pass holds A and B rows per batch; it
-// takes half as many lanes only for FP32 rows of 16 or more vectors (kz >= 64),
-// where the smaller groups measured faster; narrower rows and bfloat16 keep
-// lanes covering the row.
+// takes half as many lanes for FP32 rows of 16 or more vectors (kz >= 64) and
+// for bfloat16 rows of 16 vectors (kz = 128) from 2^18 entries on, where the
+// smaller groups measured faster; other rows keep lanes covering the row.
+// From 2^21 entries on, its 128-wide rows (FP32 and bfloat16) take work items
+// of 256 slots instead of 512.
 inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, int op,
                                int64_t nnz, Shape* sh) {
   const bool spmm = op != 0;
@@ -884,7 +886,7 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
   const int nvec = kz / sh->vec;
   if (variant < 0) {
     sh->lanes = pow2ceil(nvec);
-    if (op == 2 && t == SPC3D_F32 && nvec >= 16) sh->lanes /= 2;
+    if (op == 2 && nvec >= 16 && (t == SPC3D_F32 || nnz >= (int64_t(1) << 18))) sh->lanes /= 2;
     if (sh->lanes > 16) sh->lanes = 16;
     if (sh->lanes < 2) sh->lanes = 2;
     while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
@@ -895,6 +897,7 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
       sh->items = nnz < (int64_t(1) << 18) ? 64
                   : nnz < (int64_t(1) << 20) ? 128
                   : nnz < (int64_t(1) << 21) ? 256 : 512;
+      if (op == 2 && kz == 128 && sh->items == 512) sh->items = 256;
       if (sh->items == 64 && sh->lanes <= 8)
         sh->window = 1;
       else

@@ -25,7 +25,7 @@ CALLER_TO_SLOT, SLOT_TO_CALLER, SLOT_TO_COLUMN, COLUMN_TO_SLOT = 0, 1, 2, 3
 OP_SDDMM, OP_SPMM, OP_SDDMM_SPMM = 0, 1, 2
 NFEAT = 23
 FEATURES_BUFFER_BYTES = 256
-STATIC_SCRATCH_BYTES = 8 << 20
+STATIC_SCRATCH_BYTES = 16 << 20
 
 
 VARIANT_WINDOW = 0x200
