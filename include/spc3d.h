@@ -187,6 +187,27 @@ spc3d_status spc3d_plan_maps(spc3d_plan plan, spc3d_maps* maps);
 /* Release the host object; the workspace may be reused afterwards. */
 spc3d_status spc3d_plan_destroy(spc3d_plan plan);
 
+/* Checks, on the device, every local id of the plan that the gather,
+ * scatter-reduce, permute and compute kernels turn into an address (the
+ * localization's output, Section "The setup phase"): rowptr [R+1] runs from
+ * 0 to nnz and strictly increases; colidx[s] lies in [0, C); the head bitmap
+ * marks exactly the slots rowptr[r] and nothing past nnz; tile_row[t] is the
+ * row of slot 64t; perm[s] lies in [0, nnz); gmap_r / gmap_c lie in the
+ * block's row / column range and ascend (unless owner-grouped); and the same
+ * for the column-major arrays of a plan built with SPC3D_BUILD_CSC.  Reads
+ * only the plan's arrays, never through their values, so a damaged plan
+ * cannot make it fault.  Synchronizes `stream` (not for use under graph
+ * capture); the check uses one device word per GPU held by the library, so
+ * checks that overlap on one GPU race.  Returns OK, or OUT_OF_RANGE with
+ * spc3d_last_error() naming the first violated invariant and its index. */
+spc3d_status spc3d_plan_check(spc3d_plan plan, hipStream_t stream);
+
+/* 1 when the environment variable SPC3D_DEBUG_BOUNDS is set to anything but
+ * "0" (read once per process): every call that launches kernels over a plan
+ * then runs spc3d_plan_check on it first, on its stream, and returns that
+ * check's error instead of launching.  0 otherwise (no checking, no cost). */
+int spc3d_debug_bounds(void);
+
 /* -------------------------------------------------------------- hot path */
 
 /* PreComm, local side: SpC-BB packing of data units (paper: Section "Sparse

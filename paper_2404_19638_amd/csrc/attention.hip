@@ -449,6 +449,7 @@ spc3d_status spc3d_attention_fwd(spc3d_plan h, const void* d_Q, const void* d_K,
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   float* carry = static_cast<float*>(d_buf);
   if (t == SPC3D_F32)
     launch_attn<float, 4>(sh, stream, p, nitems, d_Q, d_K, d_V, kz, d_out, d_stats, carry);

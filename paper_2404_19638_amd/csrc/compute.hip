@@ -46,6 +46,7 @@ spc3d_status run_spmm(Plan* p, int transpose, const float* d_vals, const void* d
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   const int64_t nblocks = (nitems + 3) / 4;
   Orient o = transpose ? p->csc() : p->csr();
   if (transpose == 2) o.vidx = nullptr;   // values already in column-major slot order
@@ -138,6 +139,7 @@ spc3d_status spc3d_sddmm(spc3d_plan h, const float* d_vals, const void* d_A, con
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   const int64_t nitems = (p->nnz + sh.items - 1) / sh.items;
   const int64_t nblocks = (nitems + 3) / 4;
   const Orient o = p->csr();

@@ -95,6 +95,18 @@ class DeviceGuard {
     if (e_ != hipSuccess) return ::spc3d::hip_fail(e_, #call); \
   } while (0)
 
+// Checks the plan's local ids on the device (spc3d_plan_check); synchronizes
+// the stream.
+spc3d_status check_plan(Plan* p, hipStream_t stream);
+// check_plan when SPC3D_DEBUG_BOUNDS is set (to anything but "0") in the
+// environment, read once per process; SPC3D_OK otherwise.
+spc3d_status debug_check(Plan* p, hipStream_t stream);
+#define SPC3D_DEBUG_CHECK(plan, stream)                                   \
+  do {                                                                    \
+    spc3d_status d_ = ::spc3d::debug_check((plan), (stream));             \
+    if (d_ != SPC3D_OK) return d_;                                        \
+  } while (0)
+
 #define SPC3D_LAUNCHED(what)                                     \
   do {                                                           \
     hipError_t e_ = hipGetLastError();                           \

@@ -258,6 +258,7 @@ spc3d_status spc3d_plan_features(spc3d_plan h, int transpose, int32_t kz, spc3d_
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   unsigned long long* hist = static_cast<unsigned long long*>(d_buf);
   int* mx = reinterpret_cast<int*>(hist + kBins);
   const Orient o = transpose ? p->csc() : p->csr();

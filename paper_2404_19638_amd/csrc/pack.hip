@@ -184,6 +184,7 @@ spc3d_status spc3d_gather(spc3d_plan h, spc3d_axis axis, const void* d_src, spc3
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   const int64_t* gmap = axis == SPC3D_ROWS ? p->gmap_r : p->gmap_c;
   const int64_t lo = axis == SPC3D_ROWS ? p->row_lo : p->col_lo;
   const bool src_al = aligned16(d_src) && aligned16(d_packed);
@@ -236,6 +237,7 @@ spc3d_status spc3d_scatter_reduce(spc3d_plan h, spc3d_axis axis, const float* d_
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   const int64_t* gmap = axis == SPC3D_ROWS ? p->gmap_r : p->gmap_c;
   const int64_t lo = axis == SPC3D_ROWS ? p->row_lo : p->col_lo;
   if (aligned16(d_packed) && aligned16(d_dst) && kz % 4 == 0 && ld_dst % 4 == 0 && k0 % 4 == 0)

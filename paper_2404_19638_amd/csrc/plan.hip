@@ -913,6 +913,7 @@ spc3d_status spc3d_permute_values(spc3d_plan h, int direction, const float* d_in
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   const int gather = direction == SPC3D_CALLER_TO_SLOT || direction == SPC3D_SLOT_TO_COLUMN;
   hipLaunchKernelGGL(k_permute, dim3(grid_for(p->nnz, 256)), dim3(256), 0, stream, p->nnz,
                      csc ? p->slot_t : p->perm, gather, d_in, d_out);

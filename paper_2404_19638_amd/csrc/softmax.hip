@@ -357,6 +357,7 @@ spc3d_status spc3d_row_softmax(spc3d_plan h, const float* d_e, float* d_alpha, v
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   SoftmaxStat::St* stats;
   st = row_reduce<SoftmaxStat>(p, d_e, nullptr, d_buf, stream, &stats);
   if (st != SPC3D_OK) return st;
@@ -382,6 +383,7 @@ spc3d_status spc3d_row_softmax_bwd(spc3d_plan h, const float* d_alpha, const flo
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   DotSum::St* stats;
   st = row_reduce<DotSum>(p, d_alpha, d_dalpha, d_buf, stream, &stats);
   if (st != SPC3D_OK) return st;
@@ -403,6 +405,7 @@ spc3d_status spc3d_row_softmax_apply(spc3d_plan h, const float* d_e, const float
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   hipLaunchKernelGGL(k_softmax_apply, dim3(apply_blocks(p->nnz)), dim3(256), 0, stream, p->nnz,
                      p->head, p->tile_row, reinterpret_cast<const SoftmaxStat::St*>(d_stats), d_e,
                      d_alpha);
@@ -420,6 +423,7 @@ spc3d_status spc3d_mul_values(spc3d_plan h, const float* d_a, const float* d_b, 
   DeviceGuard dg;
   st = dg.enter(p);
   if (st != SPC3D_OK) return st;
+  SPC3D_DEBUG_CHECK(p, stream);
   hipLaunchKernelGGL(k_mul_values, dim3(blocks_for(p->nnz)), dim3(256), 0, stream, p->nnz, d_a,
                      d_b, d_out);
   SPC3D_LAUNCHED("mul_values");

@@ -67,6 +67,7 @@ def lib():
         "spc3d_plan_query": [vp, P(i64), P(i64), P(i64)],
         "spc3d_plan_maps": [vp, vp],
         "spc3d_plan_destroy": [vp],
+        "spc3d_plan_check": [vp, vp],
         "spc3d_gather": [vp, ctypes.c_int, vp, ctypes.c_int, i64, i32, i32, vp, ctypes.c_int, vp],
         "spc3d_sddmm": [vp, vp, vp, vp, ctypes.c_int, i32, vp, ctypes.c_int, ctypes.c_int, vp],
         "spc3d_spmm_buffer_size": [vp, ctypes.c_int, i32, ctypes.c_int, P(sz)],
@@ -111,6 +112,8 @@ def lib():
     L.spc3d_last_error.restype = ctypes.c_char_p
     L.spc3d_version.argtypes = []
     L.spc3d_version.restype = ctypes.c_int
+    L.spc3d_debug_bounds.argtypes = []
+    L.spc3d_debug_bounds.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -437,6 +440,17 @@ def scatter_reduce(plan: Plan, axis: int, packed: torch.Tensor, dst: torch.Tenso
                                       _ptr(dst), dst.stride(0), k0, _stream(stream)),
            "spc3d_scatter_reduce")
     return dst
+
+
+def plan_check(plan: Plan, stream=None) -> None:
+    """Checks the plan's local ids on the device (spc3d_plan_check); raises
+    Spc3dError (ERR_OUT_OF_RANGE) naming the first violated invariant."""
+    _check(lib().spc3d_plan_check(plan.handle, _stream(stream)), "spc3d_plan_check")
+
+
+def debug_bounds() -> bool:
+    """Whether SPC3D_DEBUG_BOUNDS makes every launching call check its plan."""
+    return bool(lib().spc3d_debug_bounds())
 
 
 def permute_values(plan: Plan, direction: int, x: torch.Tensor, out=None, stream=None):

@@ -60,6 +60,11 @@ def test_host_validation(lib):
     lib.spc3d_status_string.restype = ctypes.c_char_p
     assert lib.spc3d_status_string(3) == b"workspace or buffer too small"
     assert lib.spc3d_version() >= 100
+    lib.spc3d_plan_check.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.spc3d_plan_check(None, None) == 6                      # bad handle
+    assert lib.spc3d_plan_check(ctypes.cast(forged, ctypes.c_void_p), None) == 6
+    assert lib.spc3d_debug_bounds() == (1 if os.environ.get("SPC3D_DEBUG_BOUNDS", "0")
+                                        not in ("", "0") else 0)
 
 
 def test_variant_check_rules(lib):
