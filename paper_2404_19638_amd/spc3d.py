@@ -138,6 +138,12 @@ def _need(cond: bool, msg: str):
         raise ValueError(msg)
 
 
+def _rows_of(t: torch.Tensor, kz: int) -> bool:
+    """A packed operand is read as rows of kz values: a 2-D tensor must have
+    exactly kz columns (a wider one would be read with the wrong stride)."""
+    return t.dim() != 2 or t.shape[1] == kz
+
+
 def _dtype_code(t: torch.Tensor) -> int:
     if t.dtype == torch.float32:
         return F32
@@ -290,6 +296,7 @@ def gather(plan: Plan, axis: int, src: torch.Tensor, k0: int, kz: int,
         out = torch.empty((n, kz), dtype=packed_dtype, device=src.device)
     _need(src.dim() == 2 and src.stride(1) == 1, "src must be a row-major 2-D tensor")
     _need(src.shape[0] >= rng[1] - rng[0], "src needs one row per id of the axis range")
+    _need(0 <= k0 and k0 + kz <= src.shape[1], "columns k0..k0+kz lie outside src")
     _need(out.is_contiguous() and out.numel() >= n * kz, "packed output too small")
     _check(lib().spc3d_gather(plan.handle, axis, _ptr(src), _dtype_code(src), src.stride(0), k0,
                               kz, _ptr(out), _dtype_code(out), _stream(stream)), "spc3d_gather")
@@ -302,6 +309,7 @@ def sddmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | None = N
     _need(A.dtype == B.dtype, "A and B must share a dtype")
     _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
     _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(_rows_of(A, kz) and _rows_of(B, kz), "A and B must have kz columns")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
           "vals must hold nnz FP32 values")
     if out is None:
@@ -327,12 +335,13 @@ def spmm(plan: Plan, vals, X: torch.Tensor, transpose: int = 0, kz: int | None =
     n = plan.C if transpose else plan.R      # transpose 1 or 2: over columns
     nx = plan.R if transpose else plan.C
     _need(X.is_contiguous() and X.numel() >= nx * kz, "X too small for kz")
+    _need(_rows_of(X, kz), "X must have kz columns")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
           "vals must hold nnz FP32 values")
     if out is None:
         out = torch.empty((n, kz), dtype=torch.float32, device=X.device)
-    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n * kz,
-          "out too small")
+    _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= n * kz
+          and _rows_of(out, kz), "out must hold n rows of kz FP32 values")
     need = spmm_buffer_size(plan, transpose, kz, variant)
     if buf is None:
         buf = plan.buffer(("spmm", transpose), need)
@@ -351,6 +360,7 @@ def sddmm_spmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | Non
     _need(A.dtype == B.dtype, "A and B must share a dtype")
     _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
     _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(_rows_of(A, kz) and _rows_of(B, kz), "A and B must have kz columns")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
           "vals must hold nnz FP32 values")
     if out is None:
@@ -359,8 +369,8 @@ def sddmm_spmm(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: int | Non
         Y = torch.empty((plan.R, kz), dtype=torch.float32, device=A.device)
     _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
           "out must hold nnz FP32 values")
-    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz,
-          "Y too small")
+    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz
+          and _rows_of(Y, kz), "Y must hold R rows of kz FP32 values")
     need = spmm_buffer_size(plan, 0, kz, variant)
     if buf is None:
         buf = plan.buffer(("spmm", 0), need)
@@ -381,12 +391,14 @@ def sddmm_spmm_scatter(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, dst: 
     _need(A.dtype == B.dtype, "A and B must share a dtype")
     _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
     _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(_rows_of(A, kz) and _rows_of(B, kz), "A and B must have kz columns")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
           "vals must hold nnz FP32 values")
     _need(dst.dim() == 2 and dst.stride(1) == 1 and dst.dtype == torch.float32,
           "dst must be a row-major FP32 2-D tensor")
     _need(dst.shape[0] >= plan.row_range[1] - plan.row_range[0],
           "dst needs one row per id of the row range")
+    _need(0 <= k0 and k0 + kz <= dst.shape[1], "columns k0..k0+kz lie outside dst")
     if out is None:
         out = torch.empty(plan.nnz, dtype=torch.float32, device=A.device)
     _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
@@ -411,6 +423,7 @@ def sddmm_spmm_static(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: in
     _need(A.dtype == B.dtype, "A and B must share a dtype")
     _need(A.is_contiguous() and B.is_contiguous(), "A and B must be packed (contiguous)")
     _need(A.numel() >= plan.R * kz and B.numel() >= plan.C * kz, "A or B too small for kz")
+    _need(_rows_of(A, kz) and _rows_of(B, kz), "A and B must have kz columns")
     _need(vals is None or (vals.dtype == torch.float32 and vals.numel() >= plan.nnz),
           "vals must hold nnz FP32 values")
     if out is None:
@@ -419,8 +432,8 @@ def sddmm_spmm_static(plan: Plan, vals, A: torch.Tensor, B: torch.Tensor, kz: in
         Y = torch.empty((plan.R, kz), dtype=torch.float32, device=A.device)
     _need(out.dtype == torch.float32 and out.is_contiguous() and out.numel() >= plan.nnz,
           "out must hold nnz FP32 values")
-    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz,
-          "Y too small")
+    _need(Y.dtype == torch.float32 and Y.is_contiguous() and Y.numel() >= plan.R * kz
+          and _rows_of(Y, kz), "Y must hold R rows of kz FP32 values")
     _check(lib().spc3d_sddmm_spmm_static(plan.handle, _ptr(vals), _ptr(A), _ptr(B),
                                          _dtype_code(A), kz, _ptr(out), _ptr(Y), mode, variant,
                                          _stream(stream)), "spc3d_sddmm_spmm_static")
@@ -436,6 +449,7 @@ def scatter_reduce(plan: Plan, axis: int, packed: torch.Tensor, dst: torch.Tenso
     _need(dst.shape[0] >= rng[1] - rng[0], "dst needs one row per id of the axis range")
     _need(packed.dtype == torch.float32 and packed.is_contiguous() and packed.dim() == 2
           and packed.shape[0] >= n, "packed must be [n, kz] FP32")
+    _need(0 <= k0 and k0 + packed.shape[1] <= dst.shape[1], "columns k0..k0+kz lie outside dst")
     _check(lib().spc3d_scatter_reduce(plan.handle, axis, _ptr(packed), packed.shape[1],
                                       _ptr(dst), dst.stride(0), k0, _stream(stream)),
            "spc3d_scatter_reduce")

@@ -554,6 +554,10 @@ def test_bad_arguments_are_rejected():
     with pytest.raises(spc.Spc3dError) as ei:
         spc.spmm(plan, None, A, 1, 32)   # no CSC in this plan
     assert ei.value.status == spc.ERR_INVALID_ARG
-    with pytest.raises(spc.Spc3dError) as ei:
-        spc.gather(plan, spc.ROWS, torch.zeros((4096, 8), device=DEV), 4, 8)
-    assert ei.value.status == spc.ERR_INVALID_ARG
+    src = torch.zeros((4096, 8), device=DEV)
+    with pytest.raises(ValueError):   # the binding sees the columns do not fit
+        spc.gather(plan, spc.ROWS, src, 4, 8)
+    # and the C entry point refuses the same call on its own (k0 + kz > ld)
+    st = spc.lib().spc3d_gather(plan.handle, spc.ROWS, src.data_ptr(), spc.F32, 8, 4, 8,
+                                A.data_ptr(), spc.F32, torch.cuda.current_stream().cuda_stream)
+    assert st == spc.ERR_INVALID_ARG

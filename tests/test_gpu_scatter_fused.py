@@ -136,9 +136,15 @@ def test_scatter_fused_owner_grouped_rows_and_errors():
     dst0 = synth.dense_f32(91, 0, rr[1] - rr[0], 32)
     _check(spc, plan, ref["gmap_r"], rr[0], vals, A, B, dst0, k0, kz, -1, spc.OVERWRITE, "grouped")
     dst = torch.zeros((rr[1] - rr[0], 32), device=DEV)
-    with pytest.raises(spc.Spc3dError) as e:   # k0 + kz beyond the slab's row
+    with pytest.raises(ValueError):   # k0 + kz beyond the slab's row: the binding sees it
         spc.sddmm_spmm_scatter(plan, vals, A, B, dst, 20, kz)
-    assert e.value.status == spc.ERR_INVALID_ARG
+    out = torch.empty(plan.nnz, device=DEV)
+    buf = torch.empty(spc.spmm_buffer_size(plan, 0, kz), dtype=torch.uint8, device=DEV)
+    st = spc.lib().spc3d_sddmm_spmm_scatter(   # and the C entry point refuses it on its own
+        plan.handle, vals.data_ptr(), A.data_ptr(), B.data_ptr(), spc.F32, kz, out.data_ptr(),
+        spc.OVERWRITE, dst.data_ptr(), dst.stride(0), 20, -1, buf.data_ptr(), buf.numel(),
+        torch.cuda.current_stream().cuda_stream)
+    assert st == spc.ERR_INVALID_ARG
     with pytest.raises(spc.Spc3dError) as e:
         spc.sddmm_spmm_scatter(plan, vals, A, B, dst, k0, kz, out_mode=7)
     assert e.value.status == spc.ERR_INVALID_ARG
