@@ -865,10 +865,12 @@ inline int pow2ceil(int n) {
 }
 
 // op: 0 SDDMM, 1 SpMM, 2 fused SDDMM+SpMM.  Defaults (variant -1), from
-// measurements on MI355X: SDDMM on 64-slot work items with lanes covering kz;
-// SpMM and the fused pass on work items that grow with the block, about
-// nnz / 4096 slots clamped to [64, 512] so that small blocks still launch
-// enough wavefronts, in the windowed family below 2^18 entries and in the
+// measurements on MI355X: SDDMM on 64-slot work items with lanes covering kz
+// (8 lanes for 16-byte FP32 rows of 16 or more vectors below 2^20 entries); SpMM and
+// the fused pass on work items that grow with the block, about nnz / 4096
+// slots clamped to [64, 512] so that small blocks still launch enough
+// wavefronts, in the windowed family below 2^18 entries (and below 2^20 for
+// 16-byte rows of at most 4 vectors in the fused pass and FP32 SpMM) and in the
 // group-run family above.  The fused pass holds A and B rows per batch; it
 // takes half as many lanes for FP32 rows of 16 or more vectors (kz >= 64) and
 // for bfloat16 rows of 16 vectors (kz = 128) from 2^18 entries on, where the
@@ -887,6 +889,8 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
   if (variant < 0) {
     sh->lanes = pow2ceil(nvec);
     if (op == 2 && nvec >= 16 && (t == SPC3D_F32 || nnz >= (int64_t(1) << 18))) sh->lanes /= 2;
+    if (op == 0 && t == SPC3D_F32 && sh->vec > 1 && nvec >= 16 && nnz < (int64_t(1) << 20))
+      sh->lanes = 8;
     if (sh->lanes > 16) sh->lanes = 16;
     if (sh->lanes < 2) sh->lanes = 2;
     while ((nvec + sh->lanes - 1) / sh->lanes > 4) sh->lanes *= 2;
@@ -899,6 +903,8 @@ inline spc3d_status pick_shape(int kz, spc3d_dtype t, bool vec_ok, int variant, 
                   : nnz < (int64_t(1) << 21) ? 256 : 512;
       if (op == 2 && kz == 128 && sh->items == 512) sh->items = 256;
       if (sh->items == 64 && sh->lanes <= 8)
+        sh->window = 1;
+      else if (sh->items == 128 && sh->lanes <= 4 && sh->vec > 1 && (op == 2 || t == SPC3D_F32))
         sh->window = 1;
       else
         while (sh->items / (64 / sh->lanes) < 8) sh->items *= 2;

@@ -30,6 +30,11 @@ TARGET_CAP = 3.0  # slowdowns beyond 8x are all "bad"; capping keeps them from d
 # predicted faster by more than this (log2 of 1.03: about the spread of
 # repeated timings of one call).
 KEEP_DEFAULT_MARGIN = math.log2(1.03)
+# Margins tried per operation on the training blocks after the fit (log2 of
+# the predicted speed-up a candidate must show over the default); inf keeps
+# the default always, for an operation whose default the network cannot beat.
+MARGIN_GRID = (0.0, math.log2(1.02), math.log2(1.03), math.log2(1.05), math.log2(1.08),
+               math.log2(1.12), math.inf)
 
 
 def candidates(op: str) -> list:
@@ -157,6 +162,7 @@ class Selector:
                  margin: float = KEEP_DEFAULT_MARGIN):
         self.hidden = tuple(hidden)
         self.margin = margin
+        self.margins = {}   # op -> keep-default margin chosen on the training blocks
         self.seed = seed
         self.device = torch.device(device)
         self.models = {}
@@ -188,13 +194,44 @@ class Selector:
                 self.device)
         return self._masks[key]
 
-    def predict_indices(self, op: str, X: torch.Tensor, masks: torch.Tensor) -> torch.Tensor:
+    def margin_for(self, op: str) -> float:
+        return self.margins.get(op, self.margin)
+
+    def predict_indices(self, op: str, X: torch.Tensor, masks: torch.Tensor,
+                        margin: float | None = None) -> torch.Tensor:
         """Per row of X, the index into self.cands[op] of the least
         predicted slowdown among the allowed ones (device int32, -1 if none);
-        the default shape is kept unless beaten by more than self.margin."""
-        P = self.models[op].predict(X)
+        the default shape is kept unless beaten by more than the operation's
+        margin (an infinite margin keeps it always)."""
+        m = self.margin_for(op) if margin is None else margin
         pref = self.cands[op].index(-1) if -1 in self.cands[op] else -1
-        return spc.mlp_masked_argmin(P, masks.contiguous(), pref=pref, margin=self.margin)
+        if math.isinf(m) and pref >= 0:
+            return torch.full((X.shape[0],), pref, dtype=torch.int32, device=X.device)
+        P = self.models[op].predict(X)
+        return spc.mlp_masked_argmin(P, masks.contiguous(), pref=pref, margin=m)
+
+    def fit_margin(self, op: str, recs: list, grid=MARGIN_GRID) -> float:
+        """Chooses the operation's keep-default margin on training records: the
+        one of the grid with the least geometric-mean regret against the
+        autotuner (ties go to the larger margin)."""
+        rs = [r for r in recs if r["op"] == op]
+        X = torch.from_numpy(np.stack([r["features"] for r in rs]).astype(np.float32)).to(
+            self.device)
+        masks = torch.from_numpy(np.stack([valid_mask(op, r["kz"], r["dtype"], self.cands[op])
+                                           for r in rs])).to(self.device)
+        best, best_reg = None, None
+        for m in grid:
+            idx = self.predict_indices(op, X, masks, margin=m).cpu().numpy()
+            logs = []
+            for r, k in zip(rs, idx):
+                t = r["timings"]
+                v = self.cands[op][k] if k >= 0 else -1
+                logs.append(math.log(t.get(v, t[-1]) / min(t.values())))
+            reg = float(np.mean(logs))
+            if best_reg is None or reg <= best_reg:
+                best, best_reg = m, reg
+        self.margins[op] = best
+        return best
 
     def in_range(self, op: str, f: np.ndarray, margin: float = 0.0) -> bool:
         """True when every feature lies within the training range (+- margin).
@@ -224,7 +261,9 @@ class Selector:
                     models={op: m.state() for op, m in self.models.items()},
                     cands={op: list(c) for op, c in self.cands.items()},
                     lo={op: v.tolist() for op, v in self.lo.items()},
-                    hi={op: v.tolist() for op, v in self.hi.items()})
+                    hi={op: v.tolist() for op, v in self.hi.items()},
+                    margins={op: (None if math.isinf(m) else m)
+                             for op, m in self.margins.items()})
 
     @classmethod
     def from_state(cls, st: dict, device="cuda") -> "Selector":
@@ -234,6 +273,8 @@ class Selector:
             s.cands[op] = list(st["cands"][op])
             s.lo[op] = np.array(st["lo"][op], np.float32)
             s.hi[op] = np.array(st["hi"][op], np.float32)
+        for op, m in st.get("margins", {}).items():
+            s.margins[op] = math.inf if m is None else float(m)
         return s
 
 
@@ -356,7 +397,7 @@ def save_weights(state: dict, path: str, note: str = ""):
         return dict(shape=list(a.shape), b64=base64.b64encode(a.tobytes()).decode())
 
     out = dict(note=note, hidden=state["hidden"], seed=state["seed"], models={}, lo={}, hi={},
-               cands=state["cands"])
+               cands=state["cands"], margins=state.get("margins", {}))
     for op, m in state["models"].items():
         out["models"][op] = dict(sizes=m["sizes"], W=[enc(w) for w in m["W"]],
                                  b=[enc(b) for b in m["b"]])
@@ -377,7 +418,8 @@ def load_weights(path: str) -> dict:
     with open(path) as f:
         w = json.load(f)
     st = dict(hidden=w["hidden"], seed=w["seed"], models={}, lo={}, hi={},
-              cands=w.get("cands") or {op: _legacy_candidates(op) for op in w["models"]})
+              cands=w.get("cands") or {op: _legacy_candidates(op) for op in w["models"]},
+              margins=w.get("margins", {}))
     for op, m in w["models"].items():
         st["models"][op] = dict(sizes=m["sizes"], W=[dec(x).tolist() for x in m["W"]],
                                 b=[dec(x).tolist() for x in m["b"]])
@@ -508,10 +550,14 @@ def main(argv=None):
         hist = sel.fit(op, X, T, M, steps=args.steps, log_every=max(args.steps // 6, 1), log=log)
         torch.cuda.synchronize()
         fit_s = time.time() - t1
+        marg = sel.fit_margin(op, rtrain)
+        log(f"{op:10s} keep-default margin chosen on the training blocks: "
+            f"{'always the default' if math.isinf(marg) else f'{2 ** marg:.2f}x'}")
         fixed = best_fixed(rtrain, op)
         report["ops"][op] = dict(train=judge(sel, rtrain, op, fixed),
                                  held_out=judge(sel, rheld, op, fixed),
-                                 loss=hist, fit_seconds=fit_s)
+                                 loss=hist, fit_seconds=fit_s,
+                                 margin=None if math.isinf(marg) else marg)
         h = report["ops"][op]["held_out"]
         log(f"{op:10s} held-out n={h['n']}: regret geomean {h['regret_geomean']:.4f} "
             f"p90 {h['regret_p90']:.4f} top1 {h['top1']:.3f} | default regret "

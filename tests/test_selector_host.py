@@ -61,11 +61,13 @@ def test_weight_file_round_trip(tmp_path):
                                    W=[rng.standard_normal((4, S.NFEAT)).astype(np.float32).tolist(),
                                       rng.standard_normal((2, 4)).astype(np.float32).tolist()],
                                    b=[[0.5] * 4, [1.5, -2.0]])},
-              lo={"spmm": [0.0] * S.NFEAT}, hi={"spmm": [1.0] * S.NFEAT})
+              lo={"spmm": [0.0] * S.NFEAT}, hi={"spmm": [1.0] * S.NFEAT},
+              margins={"spmm": 0.0, "sddmm": None})
     p = tmp_path / "w.json"
     S.save_weights(st, str(p), note="test")
     back = S.load_weights(str(p))
     assert back["cands"] == st["cands"] and back["hidden"] == [4]
+    assert back["margins"] == {"spmm": 0.0, "sddmm": None}   # None: always the default
     for x, y in zip(back["models"]["spmm"]["W"], st["models"]["spmm"]["W"]):
         np.testing.assert_array_equal(np.float32(x), np.float32(y))
     assert back["models"]["spmm"]["b"][1] == [1.5, -2.0]
@@ -94,3 +96,14 @@ def test_selector_workload_generator_and_split():
     assert min(lg) < 10.1 and max(lg) > 17.9
     assert 0.4 < np.mean(np.array(lg) < 14) < 0.6
     assert math.isclose(S.TARGET_CAP, 3.0)
+
+
+def test_margins_survive_the_state_round_trip():
+    import math
+    sel = S.Selector((4,), device="cpu")
+    sel.margins = {"spmm": 0.0, "sddmm": math.inf}
+    st = sel.state()
+    assert st["margins"] == {"spmm": 0.0, "sddmm": None}
+    back = S.Selector.from_state(st, device="cpu")
+    assert back.margin_for("spmm") == 0.0 and math.isinf(back.margin_for("sddmm"))
+    assert back.margin_for("sddmm_spmm") == S.KEEP_DEFAULT_MARGIN   # not chosen: the constant
