@@ -207,7 +207,9 @@ class Plan:
         return self._view(d.value, ng.value + 1, torch.int32)
 
     def buffer(self, key, nbytes):
-        """Cached 256-byte aligned scratch tensor (torch allocations are aligned)."""
+        """Cached 256-byte aligned scratch tensor (torch allocations are aligned).
+        One per plan and key: calls on one plan issued concurrently from
+        several streams must each pass their own ``buf``."""
         b = self._bufs.get(key)
         if b is None or b.numel() < nbytes:
             b = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.ws.device)
